@@ -1,0 +1,236 @@
+"""Pins of the oracle's time step (Eq. (1): stream + BGK + force) against
+invariants and textbook closed forms.
+
+  * free streaming moves f_i by c_i (collisions switched off, tau -> inf);
+  * a uniform state stays uniform (forces vanish identically);
+  * per-species mass and total momentum are conserved on a periodic lattice,
+    also with tau_A != tau_B (this pins the common velocity u');
+  * G = 0 reduces to a plain BGK fluid: a shear wave decays at
+    nu k^2 with nu = c_s^2 (tau - 1/2);
+  * G = 0 between half-way bounce-back walls: the steady Couette profile is
+    exactly linear, u(y) = U (y + 1/2) / ny, with shear stress rho nu U / ny;
+  * a concentration blob is carried by a uniform flow in the flow direction;
+  * symmetry: A <-> B swap, lattice translations; rho_B = 0 stays 0.
+"""
+import numpy as np
+import pytest
+
+from paper_0807_4471_amd import inputs
+
+CS2 = 1.0 / 3.0
+BJ = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
+
+
+def test_free_streaming_direction(oracle_lib):
+    nx, ny = 7, 6
+    p = oracle_lib.Params(nx=nx, ny=ny, tau=(1e15, 1e15), Ga=(0, 0), Gr=(0, 0), Gx=0.0)
+    cx, cy, w = oracle_lib.d2q9()
+    for s in (0, 1):
+        for i in range(9):
+            f = np.zeros((2, 9, ny, nx))
+            f[s, i, 2, 5] = 1.0
+            oracle_lib.run(p, f, 1)
+            k = np.unravel_index(np.argmax(np.abs(f)), f.shape)
+            assert k == (s, i, (2 + cy[i]) % ny, (5 + cx[i]) % nx)
+            assert abs(f[k] - 1.0) < 1e-12 and abs(f.sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0), (0.05, -0.02)])
+def test_uniform_state_stays_uniform(oracle_lib, u):
+    nx, ny = 12, 10
+    p = oracle_lib.Params(nx=nx, ny=ny, **BJ)
+    rho = np.empty((2, ny, nx))
+    rho[0], rho[1] = 0.7, 0.65
+    f = oracle_lib.init(p, rho, np.full((ny, nx), u[0]), np.full((ny, nx), u[1]))
+    f0 = f.copy()
+    oracle_lib.run(p, f, 50)
+    # every site identical to every other, and equal to the initial state
+    # (a uniform state is a fixed point: F = 0, f = f^eq(rho, u))
+    assert np.abs(f - f[:, :, :1, :1]).max() < 1e-15
+    assert np.abs(f - f0).max() < 1e-14
+
+
+def test_mass_and_momentum_conservation(oracle_lib):
+    """Exact per-step conservation with tau_A != tau_B and all couplings on.
+    The window stops before demixing drives the minority density to zero
+    (where the rho_s <= 0 guard would drop that site's force)."""
+    nx, ny = 24, 20
+    p = oracle_lib.Params(nx=nx, ny=ny, tau=(0.8, 1.25), **BJ)
+    rho = inputs.random_densities(nx, ny, seed=3)
+    rng = np.random.default_rng(1)
+    ux = 0.03 + 0.005 * rng.standard_normal((ny, nx))
+    uy = -0.01 + 0.005 * rng.standard_normal((ny, nx))
+    f = oracle_lib.init(p, rho, ux, uy)
+    t0 = oracle_lib.totals(p, f)
+    j0 = np.array([np.sum((rho[0] + rho[1]) * ux), np.sum((rho[0] + rho[1]) * uy)])
+    for _ in range(5):
+        oracle_lib.run(p, f, 10)
+        t1 = oracle_lib.totals(p, f)
+        r, _, _ = oracle_lib.moments(p, f)
+        assert r.min() > 0.1
+        assert np.all(np.abs(t1["mass"] - t0["mass"]) <= 1e-13 * t0["mass"])
+        # total sum_s j_s is conserved exactly (the forces sum to zero); the
+        # reported momentum adds F/2, whose lattice sum vanishes as well
+        assert np.all(np.abs(t1["mom"] - j0) < 1e-12 * np.abs(j0).max())
+        assert t1["bad"] == 0
+
+
+def test_long_run_conservation_at_tau_one(oracle_lib):
+    nx = ny = 32
+    p = oracle_lib.Params(nx=nx, ny=ny, **BJ)
+    rho = inputs.random_densities(nx, ny, seed=9)
+    f = oracle_lib.init(p, rho)
+    t0 = oracle_lib.totals(p, f)
+    oracle_lib.run(p, f, 600)
+    t1 = oracle_lib.totals(p, f)
+    assert np.all(np.abs(t1["mass"] - t0["mass"]) <= 1e-13 * t0["mass"])
+    assert np.all(np.abs(t1["mom"]) < 1e-12)
+
+
+def test_momentum_requires_weighted_common_velocity(oracle_lib):
+    """Very different tau with a cross force: momentum stays conserved only if
+    u' weights each species by rho_s / tau_s."""
+    nx, ny = 16, 16
+    p = oracle_lib.Params(nx=nx, ny=ny, tau=(0.6, 2.0), Ga=(0, 0), Gr=(0, 0), Gx=0.8, rho0=0.7)
+    rho = inputs.random_densities(nx, ny, seed=11, amp=0.2)
+    f = oracle_lib.init(p, rho, np.full((ny, nx), 0.02), None)
+    m0 = np.array([np.sum(rho.sum(0) * 0.02), 0.0])
+    oracle_lib.run(p, f, 200)
+    t1 = oracle_lib.totals(p, f)
+    assert np.all(np.abs(t1["mom"] - m0) < 1e-12)
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.4])
+def test_shear_wave_viscosity(oracle_lib, tau):
+    """G = 0: u_x = U sin(2 pi y / L) decays as exp(-nu k^2 t), nu = c_s^2 (tau - 1/2)."""
+    L = 64
+    p = oracle_lib.Params(nx=4, ny=L, tau=(tau, tau), Ga=(0, 0), Gr=(0, 0), Gx=0.0)
+    y = np.arange(L)
+    k = 2 * np.pi / L
+    U = 1e-4
+    ux = np.tile((U * np.sin(k * y))[:, None], (1, 4))
+    rho = np.full((2, L, 4), 0.5)
+    f = oracle_lib.init(p, rho, ux, None)
+    amps, times = [], []
+    for t in (100, 300, 500, 700):
+        oracle_lib.run(p, f, t - (times[-1] if times else 0))
+        _, u, _ = oracle_lib.moments(p, f)
+        amps.append(2.0 / L * np.sum(u[:, 0] * np.sin(k * y)))
+        times.append(t)
+    rate = -np.polyfit(times, np.log(amps), 1)[0]
+    nu = CS2 * (tau - 0.5)
+    assert abs(rate / (nu * k * k) - 1.0) < 0.01, (rate, nu * k * k)
+
+
+@pytest.mark.parametrize("tau", [0.7, 1.0])
+def test_couette_exact_profile(oracle_lib, tau):
+    ny, nx, U = 16, 3, 0.05
+    p = oracle_lib.Params(nx=nx, ny=ny, walls=True, tau=(tau, tau), Ga=(0, 0), Gr=(0, 0),
+                          Gx=0.0, wall_u=(0.0, U))
+    rho = np.full((2, ny, nx), 0.5)
+    f = oracle_lib.init(p, rho)
+    m0 = oracle_lib.totals(p, f)["mass"]
+    oracle_lib.run(p, f, 12000)
+    wall = np.zeros((2, 2))
+    oracle_lib.run(p, f, 10, wall)
+    ux, sxy = oracle_lib.row_profiles(p, f)
+    y = np.arange(ny)
+    np.testing.assert_allclose(ux, U * (y + 0.5) / ny, rtol=0, atol=1e-11)
+    nu = CS2 * (tau - 0.5)
+    np.testing.assert_allclose(sxy, 1.0 * nu * U / ny, rtol=1e-8)
+    # momentum received by the walls per step and per unit length: the top
+    # wall is dragged back by -rho nu U / ny, the bottom one forward
+    np.testing.assert_allclose(wall[1, 0] / (10 * nx), -nu * U / ny, rtol=1e-8)
+    np.testing.assert_allclose(wall[0, 0] / (10 * nx), nu * U / ny, rtol=1e-8)
+    m1 = oracle_lib.totals(p, f)["mass"]
+    assert np.all(np.abs(m1 - m0) < 1e-12 * m0)
+
+
+def test_walls_conserve_mass_with_forces(oracle_lib):
+    nx, ny = 20, 14
+    p = oracle_lib.Params(nx=nx, ny=ny, walls=True, wall_u=(-0.03, 0.1), **BJ)
+    rho = inputs.random_densities(nx, ny, seed=5)
+    f = oracle_lib.init(p, rho)
+    m0 = oracle_lib.totals(p, f)["mass"]
+    oracle_lib.run(p, f, 400)
+    m1 = oracle_lib.totals(p, f)["mass"]
+    assert np.all(np.abs(m1 - m0) <= 1e-13 * m0)
+
+
+def test_advection_follows_the_flow(oracle_lib):
+    """G = 0: a concentration blob (rho_A + rho_B uniform) in a uniform flow U
+    moves by U t in the direction of the flow."""
+    nx, ny, U, T = 64, 16, 0.05, 200
+    p = oracle_lib.Params(nx=nx, ny=ny, Ga=(0, 0), Gr=(0, 0), Gx=0.0)
+    x = np.arange(nx)
+    blob = 0.05 * np.exp(-0.5 * ((x - 20.0) / 4.0) ** 2)
+    rho = np.empty((2, ny, nx))
+    rho[0] = 0.5 + blob
+    rho[1] = 0.5 - blob
+    f = oracle_lib.init(p, rho, np.full((ny, nx), U), None)
+    oracle_lib.run(p, f, T)
+    r, _, _ = oracle_lib.moments(p, f)
+    c = r[0].mean(0) - 0.5
+    centre = np.sum(c * x) / np.sum(c)
+    assert abs(centre - (20.0 + U * T)) < 0.05, centre
+
+
+def test_swap_symmetry_bitwise(oracle_lib):
+    nx, ny = 12, 9
+    pa = oracle_lib.Params(nx=nx, ny=ny, tau=(0.9, 1.1), **BJ)
+    pb = oracle_lib.Params(nx=nx, ny=ny, tau=(1.1, 0.9), Ga=BJ["Ga"][::-1], Gr=BJ["Gr"][::-1],
+                           Gx=BJ["Gx"], rho0=BJ["rho0"])
+    rho = inputs.random_densities(nx, ny, seed=2)
+    fa = oracle_lib.init(pa, rho)
+    fb = oracle_lib.init(pb, rho[::-1].copy())
+    oracle_lib.run(pa, fa, 60)
+    oracle_lib.run(pb, fb, 60)
+    assert np.array_equal(fa, fb[::-1])
+
+
+def test_translation_invariance_bitwise(oracle_lib):
+    nx, ny = 12, 10
+    p = oracle_lib.Params(nx=nx, ny=ny, **BJ)
+    rho = inputs.random_densities(nx, ny, seed=4)
+    f1 = oracle_lib.init(p, rho)
+    f2 = oracle_lib.init(p, np.roll(rho, (3, -5), axis=(1, 2)).copy())
+    oracle_lib.run(p, f1, 40)
+    oracle_lib.run(p, f2, 40)
+    assert np.array_equal(np.roll(f1, (3, -5), axis=(2, 3)), f2)
+
+
+def test_single_species_limit(oracle_lib):
+    nx, ny = 10, 10
+    p = oracle_lib.Params(nx=nx, ny=ny, **BJ)
+    rho = inputs.random_densities(nx, ny, seed=8)
+    rho[1] = 0.0
+    f = oracle_lib.init(p, rho)
+    oracle_lib.run(p, f, 30)
+    assert np.all(f[1] == 0.0)
+    assert oracle_lib.totals(p, f)["bad"] == nx * ny      # rho_B = 0 counts as non-positive
+
+
+def test_random_start_interface_area_peaks_then_decreases(oracle_lib):
+    """From random initial densities the interfacial area first grows to a
+    maximum after a short transient and then decreases (the paper's account
+    of its random-start runs).  Interface indicator I_AB = sum grad rho_A .
+    grad rho_B (definition given with Fig. 3), central differences."""
+    nx = ny = 64
+    p = oracle_lib.Params(nx=nx, ny=ny, **BJ)
+    rho = inputs.random_densities(nx, ny, seed=1)
+    f = oracle_lib.init(p, rho)
+
+    def iab(r):
+        g = [np.gradient(r[s], axis=a) for s in (0, 1) for a in (0, 1)]
+        return np.sum(g[0] * g[2] + g[1] * g[3])
+    vals, t = [], 0
+    for T in (10, 40, 75, 110, 300, 800):
+        oracle_lib.run(p, f, T - t)
+        t = T
+        r, _, _ = oracle_lib.moments(p, f)
+        vals.append(abs(iab(r)))
+    k = int(np.argmax(vals))
+    assert 0 < k < len(vals) - 1
+    assert vals[-1] < 0.5 * max(vals) and vals[0] < 0.01 * max(vals)
+    # the species demix: A-rich and B-rich domains
+    assert r[0].max() > 1.2 and r[0].min() < 0.2

@@ -1,0 +1,78 @@
+"""Laplace-law pin of the whole oracle step (forces + collision + streaming).
+
+A static droplet of A in B relaxes to a pressure jump dP = sigma / R (2-D).
+The bulk pressure is the one implied by the force model at long wavelength,
+    P = c_s^2 (rho_A + rho_B) + (c_s^2/2) sum_s G_s1 Psi_s^2
+        + c_s^2 (G_AB / rho0) rho_A rho_B,        G_s1 = G^a_s + G^r_s,
+(the bulk part of the paper's non-ideal pressure tensor, Eq. (PAB), read with
+the cross term and the c_s^2 factors the Taylor expansion of the forces
+gives).  The test checks that dP is linear in 1/R through the origin, for a
+textbook two-component case (cross repulsion only) and for the paper's
+couplings, and that the nominal surface tension decreases as rho0 grows
+(the paper's account of its Laplace test, Fig. 2 left).
+"""
+from multiprocessing import get_context
+
+import numpy as np
+import pytest
+
+CS2 = 1.0 / 3.0
+PAPER = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58)
+RADII = (8.0, 11.0, 14.0, 17.0)
+
+
+def _droplet(args):
+    import oracle
+    from paper_0807_4471_amd import inputs
+    R, kw, steps, L, rin, rout = args
+    p = oracle.Params(nx=L, ny=L, **kw)
+    f = oracle.init(p, inputs.droplet_densities(L, L, R, rin, rout))
+    oracle.run(p, f, steps)
+    r, _, _ = oracle.moments(p, f)
+    amp = p.rho0 if p.psi_amp is None else p.psi_amp
+    psi = amp * (1.0 - np.exp(-r / p.rho0))
+    G1 = np.array(p.Ga) + np.array(p.Gr)
+    P = (CS2 * (r[0] + r[1]) + 0.5 * CS2 * (G1[0] * psi[0] ** 2 + G1[1] * psi[1] ** 2)
+         + CS2 * p.Gx / p.rho0 * r[0] * r[1])
+    c = L // 2
+    a_in, a_out = r[0, c - 2:c + 2, c - 2:c + 2].mean(), r[0, :3, :3].mean()
+    R_eff = np.sqrt(np.sum((r[0] - a_out) / (a_in - a_out)) / np.pi)
+    return R_eff, P[c - 2:c + 2, c - 2:c + 2].mean() - P[:3, :3].mean()
+
+
+def _laplace_fit(jobs):
+    with get_context("fork").Pool(min(6, len(jobs))) as pool:
+        res = pool.map(_droplet, jobs)
+    out = {}
+    for job, (R, dP) in zip(jobs, res):
+        out.setdefault(tuple(sorted(job[1].items())), []).append((R, dP))
+    fits = {}
+    for key, pts in out.items():
+        R = np.array([a for a, _ in pts])
+        dP = np.array([b for _, b in pts])
+        A = np.vstack([1.0 / R, np.ones_like(R)]).T
+        (sigma, c0), *_ = np.linalg.lstsq(A, dP, rcond=None)
+        r2 = 1.0 - np.sum((dP - A @ [sigma, c0]) ** 2) / np.sum((dP - dP.mean()) ** 2)
+        fits[key] = (sigma, c0, r2, dP.max())
+    return fits
+
+
+def test_laplace_law(oracle_lib):
+    textbook = dict(Ga=(0.0, 0.0), Gr=(0.0, 0.0), Gx=2.0, rho0=1.0)
+    paper = dict(PAPER, rho0=0.7)
+    jobs = [(R, textbook, 3000, 64, 1.58, 0.01) for R in RADII]
+    jobs += [(R, paper, 3000, 64, 1.5, 0.06) for R in RADII]
+    fits = _laplace_fit(jobs)
+    for key, (sigma, c0, r2, dmax) in fits.items():
+        assert sigma > 0.0, key
+        assert r2 > 0.999, (key, r2)
+        assert abs(c0) < 0.05 * dmax, (key, c0, dmax)
+
+
+@pytest.mark.slow
+def test_surface_tension_decreases_with_rho0(oracle_lib):
+    jobs = [(R, dict(PAPER, rho0=r0), 3000, 64, 1.5, 0.06)
+            for r0 in (0.6, 0.7, 0.75) for R in RADII]
+    fits = _laplace_fit(jobs)
+    sig = [fits[tuple(sorted(dict(PAPER, rho0=r0).items()))][0] for r0 in (0.6, 0.7, 0.75)]
+    assert sig[0] > sig[1] > sig[2] > 0.0, sig

@@ -1,0 +1,225 @@
+/*
+ * sclbm.h -- C ABI of the MI355X (gfx950) two-species multi-range Shan-Chen
+ * lattice Boltzmann library (libsclbm.so).
+ *
+ * Method: Benzi, Chibbaro & Succi, "Mesoscopic lattice Boltzmann modeling of
+ * flowing soft systems" (arXiv:0807.4471).  One time step is the lattice
+ * kinetic equation, Eq. (1): free streaming plus BGK relaxation towards the
+ * local equilibrium with time scale tau_s, plus the pseudo-potential body
+ * force of the FORCE equations: like-species attraction G^a_s on the first
+ * belt (D2Q9 weights w_i), like-species repulsion G^r_s on both belts (24
+ * neighbours, weights p_1i and p_2i, 8th-order isotropic) and cross-species
+ * repulsion G_AB on the first belt, built from Psi_s[rho] = A(1-exp(-rho/rho0))
+ * and from the densities.  The force enters through the Shan-Chen shift of
+ * the equilibrium velocity.
+ *
+ * Conventions
+ *   - Every function returns an int32_t status (sclbm_status); nothing aborts
+ *     or throws.  Detail for the last failure on the calling thread is in
+ *     sclbm_last_error().  Invalid arguments are reported before any launch.
+ *   - "device pointer" arguments are HIP device addresses on the current
+ *     device; "host pointer" arguments are ordinary host memory.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  Functions marked
+ *     "async" only enqueue work on that stream; functions marked "syncs"
+ *     return after the stream has drained.
+ *   - The library never allocates or frees device memory.  The caller owns
+ *     every device buffer and must keep it alive while a handle refers to it.
+ *     The library owns only the small opaque host handles.
+ *   - Scalar fields exchanged with the caller are FP64, ny*nx, row-major,
+ *     x fastest: element (x, y) at index y*nx + x.
+ *   - Time t is the number of completed steps.  Moments are those of the
+ *     post-streaming populations f_is(r, t) of Eq. (1).
+ *   - One handle must not be used from two host threads at once; different
+ *     handles may share a stream.
+ */
+#ifndef SCLBM_H
+#define SCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCLBM_ABI_VERSION 1
+
+typedef enum {
+    SCLBM_OK = 0,
+    SCLBM_EINVAL = -1,        /* invalid argument or descriptor             */
+    SCLBM_ESIZE = -2,         /* buffer too small / size out of range        */
+    SCLBM_EDEVICE = -3,       /* a HIP call failed (detail in last_error)    */
+    SCLBM_ENONFINITE = -4,    /* diagnostics found a non-finite or
+                                 non-positive density                        */
+    SCLBM_EUNSUPPORTED = -5,  /* valid request this build does not support   */
+    SCLBM_ESTATE = -6         /* handle not initialised / wrong state        */
+} sclbm_status;
+
+enum { SCLBM_PERIODIC = 0, SCLBM_WALLS_Y = 1 };
+enum { SCLBM_F64 = 0, SCLBM_F32 = 1, SCLBM_F16DEV = 2 };
+
+/* Lattice, couplings, relaxation times and pseudo-potential of one instance.
+ * Copied at bind; the caller may free it afterwards. */
+typedef struct {
+    int32_t nx, ny;        /* lattice size: 1 <= nx, ny <= 65536 (ny >= 2 with walls),
+                              nx * ny <= 2^31 - 1                                  */
+    int32_t boundary;      /* SCLBM_PERIODIC, or SCLBM_WALLS_Y: periodic in x,
+                              half-way bounce-back walls at y = -1/2, ny - 1/2      */
+    int32_t storage;       /* SCLBM_F64: FP64 populations, FP64 arithmetic;
+                              SCLBM_F32: FP32 populations, FP32 arithmetic;
+                              SCLBM_F16DEV: binary16 deviations f - w_i rho_ref_s,
+                              FP32 arithmetic                                      */
+    double tau[2];         /* BGK relaxation times tau_A, tau_B of Eq. (1), > 1/2  */
+    double G_a[2];         /* bare like-species attraction G^a_s (first belt)      */
+    double G_r[2];         /* bare like-species repulsion G^r_s (both belts)       */
+    double G_x;            /* cross-species coupling G_AB (first belt, on rho)     */
+    double rho0;           /* reference density of Psi, > 0                       */
+    double psi_amp;        /* amplitude A of Psi = A (1 - exp(-rho / rho0)), > 0   */
+    double rho_ref[2];     /* SCLBM_F16DEV only: reference densities of the
+                              deviation storage (ignored otherwise)               */
+    double wall_u[2];      /* SCLBM_WALLS_Y only: x-velocity of bottom, top wall    */
+    double body_F0;        /* Kolmogorov body force: species s feels
+                              g_s,x = rho_s * body_F0 * sin(2 pi y / ny); 0 = off */
+    int32_t diag_every;    /* K > 0: fused FP64 diagnostics at every step t with
+                              t % K == 0 (read with sclbm_fused_diagnostics);
+                              0: off                                               */
+    int32_t reserved;      /* must be 0                                            */
+} sclbm_desc;
+
+/* FP64 totals over the lattice at time `step`. */
+typedef struct {
+    double mass[2];        /* sum_r rho_s                                          */
+    double mom[2];         /* sum_r (sum_s j_s + F_s / 2), x and y                 */
+    double sxy;            /* sum_r of the deviatoric shear stress
+                              sigma_xy = -sum_s (1 - 1/(2 tau_s))
+                                          sum_i c_ix c_iy (f_is - f^eq_i(rho_s, u)) */
+    double wall_mom[2][2]; /* [wall: 0 bottom, 1 top][x, y] momentum received by
+                              the walls, summed over wall_steps steps             */
+    int64_t wall_steps;    /* steps accumulated in wall_mom since the last reset  */
+    int64_t step;          /* time t of the totals                                 */
+    int64_t bad_sites;     /* sites with a non-finite or non-positive density      */
+} sclbm_diag;
+
+/* Tile shape of the fused step: a workgroup of 64*waves lanes (waves in
+ * {1, 2, 4}) owns a strip of tile_x columns (lane <-> column, 2 halo
+ * columns each side, so tile_x <= 64*waves - 4) and sweeps it over a chunk
+ * of tile_y rows.  tile_x >= min(32, nx), tile_y >= min(8, ny).  The result
+ * of a step does not depend on the tiling (bit for bit). */
+typedef struct {
+    int32_t tile_x, tile_y, waves, reserved;
+} sclbm_tiling;
+
+typedef struct sclbm_inst sclbm_inst;     /* opaque host handle: one lattice  */
+typedef struct sclbm_batch sclbm_batch;   /* opaque host handle: a batch plan */
+
+/* Version of this ABI (SCLBM_ABI_VERSION of the build). */
+int32_t sclbm_abi_version(void);
+
+/* Static description of a status code.  Never NULL. */
+const char* sclbm_strerror(int32_t status);
+
+/* Detail of the last failure on the calling thread ("" if none).  The string
+ * is owned by the library and valid until the next call on that thread. */
+const char* sclbm_last_error(void);
+
+/* Device bytes the state of one instance needs (two population copies,
+ * ghost rows, diagnostics partials, wall accumulators), or 0 if *desc is
+ * invalid.  Layout and alignment are internal. */
+size_t sclbm_state_bytes(const sclbm_desc* desc);
+
+/* Create a handle for an instance whose state lives in the caller's device
+ * buffer dev_buf (>= sclbm_state_bytes(desc) bytes, 256-byte aligned).  The
+ * handle is uninitialised (time undefined) until sclbm_init_*.  No device
+ * work is done.  Errors: EINVAL (bad desc / NULL), ESIZE (bytes too small). */
+int32_t sclbm_bind(const sclbm_desc* desc, void* dev_buf, size_t bytes, sclbm_inst** out);
+
+/* Initial state t = 0 with f_is = f^eq_i(rho_s, 0): rho_s(r) =
+ * mean[s] * (1 + amp * U), U in [-1, 1) from the SplitMix64 output number
+ * s*nx*ny + y*nx + x of the stream seeded with `seed` (counter-based; the
+ * same recipe as the Python input generator).  Async.  Also clears the
+ * diagnostics and wall accumulators. */
+int32_t sclbm_init_random(sclbm_inst* inst, uint64_t seed, const double mean[2], double amp,
+                          void* hip_stream);
+
+/* Initial state t = 0 with f_is = f^eq_i(rho_s, u) from caller fields:
+ * rhoA, rhoB, ux, uy are device pointers to ny*nx FP64 arrays (ux, uy may be
+ * NULL for zero velocity).  Async: the caller keeps them alive until the
+ * stream has passed this call. */
+int32_t sclbm_init_fields(sclbm_inst* inst, const double* rhoA, const double* rhoB,
+                          const double* ux, const double* uy, void* hip_stream);
+
+/* Advance n >= 0 time steps of Eq. (1): one fused stream + moments + Psi +
+ * forces + velocity shift + BGK pass per step.  Async. */
+int32_t sclbm_step(sclbm_inst* inst, int64_t n, void* hip_stream);
+
+/* Choose the tiling of sclbm_step for this instance (the library starts
+ * from a size-based default; the Python autotuner measures and sets it).
+ * No device work.  Errors: EINVAL if the tiling violates the limits above. */
+int32_t sclbm_set_tiling(sclbm_inst* inst, const sclbm_tiling* tiling);
+
+/* Current tiling of sclbm_step for this instance. */
+int32_t sclbm_get_tiling(const sclbm_inst* inst, sclbm_tiling* out);
+
+/* Time t of the instance (host-side counter; no device work). */
+int32_t sclbm_time(const sclbm_inst* inst, int64_t* t);
+
+/* Moments at the current time into caller device arrays (ny*nx FP64 each,
+ * any may be NULL): densities rho_A, rho_B; physical velocity
+ * u = (sum_s j_s + F_s/2) / sum_s rho_s; deviatoric shear stress sigma_xy.
+ * Async. */
+int32_t sclbm_read_moments(sclbm_inst* inst, double* rhoA, double* rhoB, double* ux,
+                           double* uy, double* sxy, void* hip_stream);
+
+/* FP64 totals of the current state into *out (host).  Runs one read-only
+ * pass, then syncs.  Returns ENONFINITE (with *out filled) if any density is
+ * non-finite or non-positive. */
+int32_t sclbm_diagnostics(sclbm_inst* inst, sclbm_diag* out, void* hip_stream);
+
+/* The most recent fused diagnostics (desc.diag_every > 0) into *out (host);
+ * out->step tells which time they describe (-1 if none yet).  Syncs.
+ * Returns ENONFINITE as sclbm_diagnostics does. */
+int32_t sclbm_fused_diagnostics(sclbm_inst* inst, sclbm_diag* out, void* hip_stream);
+
+/* Zero the wall-momentum accumulators (async). */
+int32_t sclbm_reset_wall_accum(sclbm_inst* inst, void* hip_stream);
+
+/* Bytes of a checkpoint of this instance. */
+size_t sclbm_checkpoint_bytes(const sclbm_inst* inst);
+
+/* Copy the state at the current time (raw storage, plus time) into the host
+ * buffer host_buf (>= sclbm_checkpoint_bytes).  Syncs. */
+int32_t sclbm_checkpoint(sclbm_inst* inst, void* host_buf, size_t bytes, void* hip_stream);
+
+/* Load a checkpoint written by sclbm_checkpoint of an instance with the same
+ * nx, ny, boundary and storage.  Syncs.  Errors: EINVAL (mismatch). */
+int32_t sclbm_restore(sclbm_inst* inst, const void* host_buf, size_t bytes, void* hip_stream);
+
+/* Free the handle (never the caller's device buffer).  NULL is a no-op. */
+int32_t sclbm_release(sclbm_inst* inst);
+
+/* ---------------- batching: many instances, one persistent launch -------- */
+
+/* Device bytes the plan of `n` instances with the given tilings needs
+ * (tile table, per-instance parameters, step barrier counters), 0 if invalid. */
+size_t sclbm_batch_bytes(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling);
+
+/* Build a batch over n initialised instances (all with the same storage and
+ * diag_every == 0) using the caller's device workspace (>= sclbm_batch_bytes).
+ * tiling[k] applies to insts[k]; all tilings must share `waves`.  Async
+ * upload on hip_stream. */
+int32_t sclbm_batch_plan(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling,
+                         void* dev_workspace, size_t bytes, void* hip_stream,
+                         sclbm_batch** out);
+
+/* Advance instance k of the batch by steps[k] >= 0 steps in ONE persistent
+ * launch (instances that finish early drop out).  Results are bitwise equal
+ * to sclbm_step on each instance alone.  Async. */
+int32_t sclbm_batch_step(sclbm_batch* batch, const int64_t* steps, void* hip_stream);
+
+/* Free the batch handle (not the workspace or the instances). */
+int32_t sclbm_batch_release(sclbm_batch* batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

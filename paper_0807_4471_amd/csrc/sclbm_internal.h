@@ -1,0 +1,78 @@
+// sclbm_internal.h -- shared between the HIP kernels and the host runtime of
+// libsclbm.so (not part of the public ABI).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace sclbm {
+
+// Slots of the FP64 diagnostics record.
+enum {
+    D_MASS_A = 0,
+    D_MASS_B = 1,
+    D_MOM_X = 2,
+    D_MOM_Y = 3,
+    D_SXY = 4,
+    D_BAD = 5,
+    NDIAG = 8
+};
+
+// Kernel modes: a full step, a step that also reduces diagnostics of the
+// state it starts from, a read-out of moments, a diagnostics-only pass.
+enum { M_STEP = 0, M_STEP_DIAG = 1, M_READ = 2, M_DIAG = 3 };
+
+// Population storage in HBM: f[s][i][row][x], s-major then direction, rows of
+// `pitch` elements, `plane` elements between consecutive (s, i) planes.  With
+// walls there are two ghost rows (row 0 below the channel, row ny + 1 above);
+// real row y sits at row y + walls.  What is stored is the post-collision
+// set f*(t-1); a step pulls f_i(x, t) = f*_i(x - c_i, t-1).
+struct Geo {
+    int32_t nx, ny, walls, rows, pitch;
+    int32_t pad_;
+    int64_t plane;
+};
+
+// Per-instance constants in the arithmetic type A of the kernel.
+//   Force on species s (pair form of the FORCE equations, offsets e and -e
+//   combined):  F_s = -Psi_s(x) * S_s - rho_s(x) * X_s, with shell
+//   coefficients K(|e|^2) = G^a_s w(|e|^2) + G^r_s p(|e|^2) folded into
+//   K1, K2, K4x2 = 2 K(4), K5, K8x2 = 2 K(8), and X1 = (G_AB/rho0) w(1),
+//   X2 = (G_AB/rho0) w(2).
+template <class A>
+struct Coef {
+    A K1[2], K2[2], K4x2[2], K5[2], K8x2[2];
+    A X1, X2;
+    A tau[2], omega[2], hs[2];  // hs = 1 - 1/(2 tau): stress prefactor
+    A psi_amp, neg_inv_rho0;
+    A wall6u[2];                // 6 u_w (bottom, top): 2 (c_i.u_w)/c_s^2 = 6 c_ix u_w
+    A base[2][9];               // F16 deviation reference w_i rho_ref_s
+    double body_F0;             // Kolmogorov amplitude (0 = off)
+    double two_pi_over_ny;
+};
+
+// Everything one instance's tile sweep needs.
+template <class S, class A>
+struct Inst {
+    const S* fin;
+    S* fout;
+    Geo g;
+    Coef<A> c;
+    int32_t W, H;               // interior columns per strip, rows per chunk
+    int32_t nstrips, nchunks;
+    double* partials;           // [nblocks][NDIAG] (diagnostic modes)
+    double* wall_acc;           // [2 walls][2 comps][nx], accumulated every step
+    double* out[5];             // READ mode: rhoA, rhoB, ux, uy, sxy (any NULL)
+};
+
+// Host-side launchers (defined in sclbm_kernels.hip).
+hipError_t launch_sweep(int storage, int cw, int mode, const void* inst, int nblocks,
+                        hipStream_t st);
+hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
+hipError_t launch_init(int storage, const void* inst, const double* rhoA, const double* rhoB,
+                       const double* ux, const double* uy, int random, uint64_t seed,
+                       double meanA, double meanB, double amp, hipStream_t st);
+
+}  // namespace sclbm

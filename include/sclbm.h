@@ -100,13 +100,17 @@ typedef struct {
     int64_t bad_sites;     /* sites with a non-finite or non-positive density      */
 } sclbm_diag;
 
-/* Tile shape of the fused step: a workgroup of 64*waves lanes (waves in
- * {1, 2, 4}) owns a strip of tile_x columns (lane <-> column, 2 halo
- * columns each side, so tile_x <= 64*waves - 4) and sweeps it over a chunk
- * of tile_y rows.  tile_x >= min(32, nx), tile_y >= min(8, ny).  The result
- * of a step does not depend on the tiling (bit for bit). */
+/* Tile shape of the fused step.
+ * stacked = 0 (sweep): a workgroup of 64*waves lanes (waves in {1, 2, 4})
+ *   owns a strip of tile_x columns (lane <-> column, 2 halo columns each
+ *   side, so tile_x <= 64*waves - 4) and sweeps it upward over a chunk of
+ *   tile_y >= min(4, ny) rows, one row per iteration.
+ * stacked = 1 (tile, for small lattices): waves in {4, 8} stacked along y,
+ *   one row each; tile_y == waves, tile_x <= 60.
+ * Always tile_x >= min(32, nx).  The result of a step does not depend on
+ * the tiling (bit for bit). */
 typedef struct {
-    int32_t tile_x, tile_y, waves, reserved;
+    int32_t tile_x, tile_y, waves, stacked;
 } sclbm_tiling;
 
 typedef struct sclbm_inst sclbm_inst;     /* opaque host handle: one lattice  */

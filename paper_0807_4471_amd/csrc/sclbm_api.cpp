@@ -39,7 +39,7 @@ int32_t hip_fail(hipError_t e, const char* what)
 
 constexpr size_t ALIGN = 256;
 constexpr int MIN_TILE_X = 32;  // smallest strip width a tiling may use
-constexpr int MIN_TILE_Y = 8;   // smallest chunk height a tiling may use
+constexpr int MIN_TILE_Y = 4;   // smallest chunk height a tiling may use
 constexpr uint64_t CKPT_MAGIC = 0x53434C424D434B31ull;  // "SCLBMCK1"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -150,10 +150,8 @@ Coef<A> coefficients(const sclbm_desc* d)
         c.omega[s] = (A)(1.0 / d->tau[s]);
         c.hs[s] = (A)(1.0 - 0.5 / d->tau[s]);
         c.wall6u[s] = (A)(6.0 * d->wall_u[s]);
-        const double wi[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
-                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
-        for (int i = 0; i < 9; ++i)
-            c.base[s][i] = d->storage == SCLBM_F16DEV ? (A)(wi[i] * d->rho_ref[s]) : (A)0;
+        c.rho_base[s] = d->storage == SCLBM_F16DEV ? (A)d->rho_ref[s] : (A)0;
+        c.tau1[s] = d->tau[s] == 1.0;
     }
     const double gx = d->G_x / d->rho0;
     c.X1 = (A)(gx * W_OF_SHELL[1]);
@@ -180,12 +178,14 @@ struct sclbm_inst {
     int64_t fused_step;
     int64_t wall_steps;
     int cw, W, H, nstrips, nchunks;
+    int stacked;          // 1: tile mode, cw waves stacked along y (H == cw)
 };
 
 namespace {
 
-void set_tiling(sclbm_inst* h, int cw, int W, int H)
+void set_tiling(sclbm_inst* h, int cw, int W, int H, int stacked = 0)
 {
+    h->stacked = stacked;
     h->cw = cw;
     h->W = W;
     h->H = H;
@@ -193,11 +193,19 @@ void set_tiling(sclbm_inst* h, int cw, int W, int H)
     h->nchunks = (h->d.ny + H - 1) / H;
 }
 
-// Default tiling: widest strips that fit, chunk height giving about 8 waves
-// per CU on 256 CUs.
+// Default tiling.  Lattices of up to 2^20 sites use stacked tiles (4 waves,
+// one row each) so that enough short-lived workgroups exist; larger ones
+// sweep the widest strips that fit over chunks sized for about 8 waves per
+// CU on 256 CUs.  The autotuner refines this per size.
 void default_tiling(sclbm_inst* h)
 {
     const int nx = h->d.nx, ny = h->d.ny;
+    if ((int64_t)nx * ny <= (1 << 20)) {
+        const int ns = (nx + 59) / 60;
+        const int W = std::max((nx + ns - 1) / ns, std::min(MIN_TILE_X, nx));
+        set_tiling(h, 4, std::min(W, 60), 4, 1);
+        return;
+    }
     int cw = nx >= 192 ? 4 : nx >= 96 ? 2 : 1;
     if (h->d.storage == SCLBM_F64 && cw == 4) cw = 2;
     const int wmax = 64 * cw - 4;
@@ -210,10 +218,22 @@ void default_tiling(sclbm_inst* h)
     set_tiling(h, cw, W, H);
 }
 
+// Seed of the FP16 stochastic rounding in the step that starts at time t: a
+// fixed function of t, so results are reproducible and independent of how
+// the steps are launched.
+uint32_t step_seed(int64_t t)
+{
+    uint64_t z = (uint64_t)t * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)(z ^ (z >> 31));
+}
+
 template <class S, class A>
 Inst<S, A> make_inst(const sclbm_inst* h, const Coef<A>& c, int from, int to, int W, int H)
 {
     Inst<S, A> I{};
+    I.seed = step_seed(h->t);
     I.fin = reinterpret_cast<const S*>(h->buf + h->L.off_f[from]);
     I.fout = reinterpret_cast<S*>(h->buf + h->L.off_f[to]);
     I.g = h->L.g;
@@ -407,8 +427,8 @@ int32_t sclbm_step(sclbm_inst* h, int64_t n, void* stream)
     for (int64_t k = 0; k < n; ++k) {
         const bool diag = h->d.diag_every > 0 && h->t % h->d.diag_every == 0;
         int nb = 0;
-        int32_t rc = sweep(h, diag ? M_STEP_DIAG : M_STEP, h->cw, h->W, h->H, h->cur, 1 - h->cur,
-                           nullptr, st, &nb);
+        int32_t rc = sweep(h, diag ? M_STEP_DIAG : M_STEP, h->stacked ? -h->cw : h->cw, h->W,
+                           h->H, h->cur, 1 - h->cur, nullptr, st, &nb);
         if (rc) return rc;
         if (diag) {
             hipError_t e = launch_reduce(reinterpret_cast<double*>(h->buf + h->L.off_partials),
@@ -428,12 +448,18 @@ int32_t sclbm_set_tiling(sclbm_inst* h, const sclbm_tiling* tl)
 {
     if (!h || !tl) return fail(SCLBM_EINVAL, "NULL argument");
     const int cw = tl->waves, W = tl->tile_x, H = tl->tile_y;
-    if (cw != 1 && cw != 2 && cw != 4) return fail(SCLBM_EINVAL, "waves must be 1, 2 or 4");
-    if (W > 64 * cw - 4) return fail(SCLBM_EINVAL, "tile_x %d > 64*waves - 4", W);
+    if (tl->stacked != 0 && tl->stacked != 1) return fail(SCLBM_EINVAL, "stacked must be 0 or 1");
+    if (tl->stacked) {
+        if (cw != 4 && cw != 8) return fail(SCLBM_EINVAL, "stacked tiles need waves 4 or 8");
+        if (H != cw) return fail(SCLBM_EINVAL, "stacked tiles need tile_y == waves");
+        if (W > 60) return fail(SCLBM_EINVAL, "stacked tile_x %d > 60", W);
+    } else {
+        if (cw != 1 && cw != 2 && cw != 4) return fail(SCLBM_EINVAL, "waves must be 1, 2 or 4");
+        if (W > 64 * cw - 4) return fail(SCLBM_EINVAL, "tile_x %d > 64*waves - 4", W);
+        if (H < std::min(MIN_TILE_Y, h->d.ny)) return fail(SCLBM_EINVAL, "tile_y %d too small", H);
+    }
     if (W < std::min(MIN_TILE_X, h->d.nx)) return fail(SCLBM_EINVAL, "tile_x %d too small", W);
-    if (H < std::min(MIN_TILE_Y, h->d.ny)) return fail(SCLBM_EINVAL, "tile_y %d too small", H);
-    if (tl->reserved != 0) return fail(SCLBM_EINVAL, "reserved must be 0");
-    set_tiling(h, cw, W, H);
+    set_tiling(h, cw, W, H, tl->stacked);
     return SCLBM_OK;
 }
 
@@ -443,7 +469,7 @@ int32_t sclbm_get_tiling(const sclbm_inst* h, sclbm_tiling* out)
     out->tile_x = h->W;
     out->tile_y = h->H;
     out->waves = h->cw;
-    out->reserved = 0;
+    out->stacked = h->stacked;
     return SCLBM_OK;
 }
 

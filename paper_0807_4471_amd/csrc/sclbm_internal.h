@@ -48,7 +48,8 @@ struct Coef {
     A tau[2], omega[2], hs[2];  // hs = 1 - 1/(2 tau): stress prefactor
     A psi_amp, neg_inv_rho0;
     A wall6u[2];                // 6 u_w (bottom, top): 2 (c_i.u_w)/c_s^2 = 6 c_ix u_w
-    A base[2][9];               // F16 deviation reference w_i rho_ref_s
+    A rho_base[2];              // FP16 deviation storage: rho_ref_s (0 otherwise)
+    int32_t tau1[2];            // 1 if tau_s == 1 exactly (BGK lands on f^eq)
     double body_F0;             // Kolmogorov amplitude (0 = off)
     double two_pi_over_ny;
 };
@@ -62,6 +63,8 @@ struct Inst {
     Coef<A> c;
     int32_t W, H;               // interior columns per strip, rows per chunk
     int32_t nstrips, nchunks;
+    uint32_t seed;              // per-step key of the FP16 stochastic rounding
+    uint32_t pad_;
     double* partials;           // [nblocks][NDIAG] (diagnostic modes)
     double* wall_acc;           // [2 walls][2 comps][nx], accumulated every step
     double* out[5];             // READ mode: rhoA, rhoB, ux, uy, sxy (any NULL)

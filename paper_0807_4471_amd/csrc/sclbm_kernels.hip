@@ -50,25 +50,20 @@ struct TF16 {
 #define W0 (4.0 / 9.0)
 #define W1 (1.0 / 9.0)
 #define W2 (1.0 / 36.0)
+constexpr int CX_[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY_[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP_[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
-template <class T>
-__device__ __forceinline__ typename T::A ld(const typename T::S* __restrict__ p,
-                                            typename T::A base)
+// 32-bit integer finaliser "lowbias32" (C. Wellons, hash-prospector): the
+// random bits of the stochastic rounding, keyed by step seed, site, species.
+__device__ __forceinline__ uint32_t hash32(uint32_t x)
 {
-    if constexpr (std::is_same<T, TF16>::value)
-        return base + (float)(*p);
-    else
-        return (typename T::A)(*p);
-}
-
-template <class T>
-__device__ __forceinline__ void st(typename T::S* __restrict__ p, typename T::A v,
-                                   typename T::A base)
-{
-    if constexpr (std::is_same<T, TF16>::value)
-        *p = (_Float16)(v - base);
-    else
-        *p = (typename T::S)v;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
 }
 
 template <class T>
@@ -89,84 +84,61 @@ __device__ __forceinline__ typename T::A expo(typename T::A v)
         return expf(v);
 }
 
-// Pull the 18 post-streaming populations of real row rr at column xw:
-// f_i(x, t) = f*_i(x - c_i, t-1).  With walls the rows +-1 beyond the channel
-// are the ghost rows holding the bounced-back populations.
-template <class T, bool WALLS>
-__device__ __forceinline__ void pull(const Inst<typename T::S, typename T::A>& I,
-                                     const typename T::S* __restrict__ fin, int rr, int xw,
-                                     int xm, int xp, typename T::A f[18])
-{
-    const Geo& g = I.g;
-    int r0, rm, rp;
-    if constexpr (WALLS) {
-        r0 = rr + 1;
-        rm = rr;
-        rp = rr + 2;
-    } else {
-        r0 = rr;
-        rm = rr == 0 ? g.ny - 1 : rr - 1;
-        rp = rr == g.ny - 1 ? 0 : rr + 1;
-    }
-    const int o0 = r0 * g.pitch, om = rm * g.pitch, op = rp * g.pitch;
-    const int off[9] = {o0 + xw, o0 + xm, om + xw, o0 + xp, op + xw,
-                        om + xm, om + xp, op + xp, op + xm};
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            f[s * 9 + i] = ld<T>(fin + (int64_t)(s * 9 + i) * g.plane + off[i], I.c.base[s][i]);
-}
-
-template <class A>
-__device__ __forceinline__ void moments(const A* f, A& rho, A& jx, A& jy)
-{
-    rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-}
-
-// One BGK relaxation towards f^eq(rho, u) (second-order D2Q9 polynomial).
-template <class A>
-__device__ __forceinline__ void bgk(A* f, A rho, A ux, A uy, A omega)
-{
-    const A usq = ux * ux + uy * uy;
-    const A com = A(1) - A(1.5) * usq;
-    const A r0 = A(W0) * rho, r1 = A(W1) * rho, r2 = A(W2) * rho;
-    auto eq = [&](A rw, A cu) { return rw * (com + A(3) * cu + A(4.5) * cu * cu); };
-    const A up = ux + uy, um = ux - uy;
-    const A feq[9] = {r0 * com,     eq(r1, ux),  eq(r1, uy),  eq(r1, -ux), eq(r1, -uy),
-                      eq(r2, up),   eq(r2, -um), eq(r2, -up), eq(r2, um)};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = f[i] - omega * (f[i] - feq[i]);
-}
-
-// Sweep one (strip, chunk) tile.  MODE selects step / step+diagnostics /
-// moment read-out / diagnostics only.  acc[] collects FP64 diagnostics of
-// the owned sites.
-template <class T, int CW, bool WALLS, int MODE>
-__device__ __forceinline__ void sweep(const Inst<typename T::S, typename T::A>& I, int strip,
-                                      int chunk, typename T::A2 (*lpsi)[64 * CW],
-                                      typename T::A2 (*lrho)[64 * CW], double* acc)
-{
+// Register representation of the populations.  FP64 / FP32 storage: v_i =
+// f_i.  FP16 deviation storage: v_i = h_i = f_i - w_i rho_ref (the deviation
+// from the exact reference populations), and all arithmetic stays in that
+// form: rho = rho_ref + sum_i h_i, j = sum_i c_i h_i (the reference carries
+// no momentum), f^eq_i - w_i rho_ref = w_i ((rho - rho_ref) + rho P_i).  Sums
+// of binary16 values are exact in FP32, so the mass bookkeeping is exact.
+template <class T, int CW, bool WALLS, int MODE, int NS = 6>
+struct Sweep {
+    using S = typename T::S;
     using A = typename T::A;
     using A2 = typename T::A2;
-    const typename T::S* __restrict__ fin = I.fin;
-    typename T::S* __restrict__ fout = I.fout;
-    const Geo& g = I.g;
-    const int nx = g.nx, ny = g.ny;
-    const int t = threadIdx.x;
-    const int x = strip * I.W - 2 + t;
-    int xw = x % nx;
-    if (xw < 0) xw += nx;
-    const int xm = xw == 0 ? nx - 1 : xw - 1;
-    const int xp = xw == nx - 1 ? 0 : xw + 1;
-    const bool own = t >= 2 && t < I.W + 2 && x < nx;
-    const int y0 = chunk * I.H;
-    const int y1 = min(y0 + I.H, ny);
-    const Coef<A>& c = I.c;
+    static constexpr bool DEV = std::is_same<T, TF16>::value;
+    // Rows are prefetched one iteration ahead (loads in flight while the
+    // previous row is finished) except in FP64, where three resident rows of
+    // doubles leave no registers for a fourth.
+    static constexpr bool PF = !std::is_same<A, double>::value;
+    static constexpr int NC = 64 * CW;
 
-    auto real_row = [&](int r) {
+    const Inst<S, A>& I;
+    A2 (*lpsi)[NC];
+    A2 (*lrho)[NC];
+    double* acc;
+    int t, nx, ny, xw, xm, xp;
+    bool own;
+    uint32_t cw, cm, cp;  // column byte offsets of x, x-1, x+1
+    const char* finb;
+    char* foutb;
+    int64_t plane_b, pitch_b;
+    S R[18];  // raw loads of the next row
+
+    __device__ Sweep(const Inst<S, A>& I_, int strip, A2 (*lp)[NC], A2 (*lr)[NC], double* acc_)
+        : I(I_), lpsi(lp), lrho(lr), acc(acc_)
+    {
+        t = threadIdx.x & (NC - 1);
+        nx = I.g.nx;
+        ny = I.g.ny;
+        const int x = strip * I.W - 2 + t;
+        xw = x % nx;
+        if (xw < 0) xw += nx;
+        xm = xw == 0 ? nx - 1 : xw - 1;
+        xp = xw == nx - 1 ? 0 : xw + 1;
+        own = t >= 2 && t < I.W + 2 && x < nx;
+        cw = (uint32_t)xw * sizeof(S);
+        cm = (uint32_t)xm * sizeof(S);
+        cp = (uint32_t)xp * sizeof(S);
+        finb = reinterpret_cast<const char*>(I.fin);
+        foutb = reinterpret_cast<char*>(I.fout);
+        plane_b = I.g.plane * (int64_t)sizeof(S);
+        pitch_b = (int64_t)I.g.pitch * (int64_t)sizeof(S);
+    }
+
+    // Ring row r (may lie outside the lattice) -> real row: periodic wrap, or
+    // the mirror image about the wall planes y = -1/2, ny - 1/2.
+    __device__ int real_row(int r) const
+    {
         if constexpr (WALLS) {
             if (r < 0) r = -1 - r;
             if (r > ny - 1) r = 2 * ny - 1 - r;
@@ -175,187 +147,339 @@ __device__ __forceinline__ void sweep(const Inst<typename T::S, typename T::A>& 
             r %= ny;
             return r < 0 ? r + ny : r;
         }
-    };
+    }
 
-    A P0[18], P1[18], P2[18];
+    // Issue the 18 loads f_i(x, t) = f*_i(x - c_i, t-1) of ring row r into R.
+    // Plane and row parts of each address are uniform; each lane adds one of
+    // three fixed 32-bit column byte offsets (x, x-1, x+1).  With walls the
+    // rows just outside the channel are the ghost rows holding bounced-back
+    // populations.
+    __device__ void load(int r)
+    {
+        const int rr = real_row(r);
+        int r0, rm, rp;
+        if constexpr (WALLS) {
+            r0 = rr + 1;
+            rm = rr;
+            rp = rr + 2;
+        } else {
+            r0 = rr;
+            rm = rr == 0 ? ny - 1 : rr - 1;
+            rp = rr == ny - 1 ? 0 : rr + 1;
+        }
+        const char* b0 = finb + (int64_t)r0 * pitch_b;
+        const char* bm = finb + (int64_t)rm * pitch_b;
+        const char* bp = finb + (int64_t)rp * pitch_b;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const char* rb = CY_[i] > 0 ? bm : CY_[i] < 0 ? bp : b0;
+                const uint32_t co = CX_[i] > 0 ? cm : CX_[i] < 0 ? cp : cw;
+                R[s * 9 + i] = *(const S*)(rb + (int64_t)(s * 9 + i) * plane_b + co);
+            }
+    }
 
-    // Pull row r into f, stage its Psi and rho in ring slot `slot`.
-    auto stage = [&](int r, int slot, A* f) {
-        pull<T, WALLS>(I, fin, real_row(r), xw, xm, xp, f);
-        A ra, rb, jx, jy;
-        moments<A>(f, ra, jx, jy);
-        moments<A>(f + 9, rb, jx, jy);
+    __device__ void convert(A* v) const
+    {
+#pragma unroll
+        for (int k = 0; k < 18; ++k) v[k] = (A)R[k];
+    }
+
+    // FP64 / FP32: the loads land directly in a row buffer.
+    __device__ void load_into(int r, A* v)
+    {
+        load(r);
+        if constexpr (!DEV) {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) v[k] = R[k];
+        }
+    }
+
+    // rho_s - rho_base_s = sum_i v_i (fixed order)
+    __device__ static A mass(const A* v)
+    {
+        return v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6] + v[7] + v[8];
+    }
+
+    // Stage a row: (Psi_A, Psi_B) and (rhod_A, rhod_B) into ring slot
+    // `slot`, rhod = rho - rho_base (= rho except for FP16 deviations, where
+    // it is the exact FP32 sum of the binary16 deviations).
+    __device__ void stage(int slot, const A* v) const
+    {
+        const Coef<A>& c = I.c;
+        const A da = mass(v), db = mass(v + 9);
+        A ra = da, rb = db;
+        if constexpr (DEV) {
+            ra += c.rho_base[0];
+            rb += c.rho_base[1];
+        }
         const A pa = c.psi_amp * (A(1) - expo<T>(ra * c.neg_inv_rho0));
         const A pb = c.psi_amp * (A(1) - expo<T>(rb * c.neg_inv_rho0));
         lpsi[slot][t] = A2{pa, pb};
-        lrho[slot][t] = A2{ra, rb};
-    };
+        lrho[slot][t] = A2{da, db};
+    }
 
-    // Prologue: rows y0-2 .. y0+1 in slots 0..3; keep rows y0, y0+1.
-    stage(y0 - 2, 0, P2);
-    stage(y0 - 1, 1, P2);
-    stage(y0, 2, P0);
-    stage(y0 + 1, 3, P1);
-
-    int sb = 0;  // slot of row y-2
-    for (int y = y0; y < y1; ++y) {
-        const int snew = sb + 4 >= 6 ? sb - 2 : sb + 4;
-        stage(y + 2, snew, P2);
-        __syncthreads();
-        if (own) {
-            int sl[5];
+    // Relax species populations v towards equilibrium (in the register
+    // representation); v[0] becomes the remainder rhod - sum_{i>0} v_i, so
+    // the collision conserves mass to one rounding whatever the rounding of
+    // the weights (in FP32 4/9 + 4/9 + 4/36 rounds to 1 + 7.4e-9).
+    __device__ static void bgk(A* v, A rho, A rhod, A ux, A uy, A omega, bool tau1)
+    {
+        const A usq15 = A(1.5) * (ux * ux + uy * uy);
+        const A w1r = A(W1) * rho, w2r = A(W2) * rho;
+        const A w1d = A(W1) * rhod, w2d = A(W2) * rhod;
+        const A up = ux + uy, um = ux - uy;
+        // P_i = 3 cu + 4.5 cu^2 - 1.5 u^2 ;  veq_i = w_i (rhod + rho P_i)
+        auto veq = [&](A wr, A wd, A cu) {
+            const A P = cu * (A(3) + A(4.5) * cu) - usq15;
+            return wr * P + wd;
+        };
+        const A eq[9] = {A(0),           veq(w1r, w1d, ux), veq(w1r, w1d, uy),
+                         veq(w1r, w1d, -ux), veq(w1r, w1d, -uy), veq(w2r, w2d, up),
+                         veq(w2r, w2d, -um), veq(w2r, w2d, -up), veq(w2r, w2d, um)};
+        if (tau1) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sl[k] = (sb + k) % 6;
-            auto Ps = [&](int dx, int dy) { return lpsi[sl[dy + 2]][t + dx]; };
-            auto Rs = [&](int dx, int dy) { return lrho[sl[dy + 2]][t + dx]; };
-            auto dif = [](A2 a, A2 b) { return A2{a.x - b.x, a.y - b.y}; };
-            // Psi differences over the 12 opposite pairs (both species).
-            const A2 a10 = dif(Ps(1, 0), Ps(-1, 0)), a01 = dif(Ps(0, 1), Ps(0, -1));
-            const A2 a11 = dif(Ps(1, 1), Ps(-1, -1)), b11 = dif(Ps(-1, 1), Ps(1, -1));
-            const A2 a20 = dif(Ps(2, 0), Ps(-2, 0)), a02 = dif(Ps(0, 2), Ps(0, -2));
-            const A2 a21 = dif(Ps(2, 1), Ps(-2, -1)), a12 = dif(Ps(1, 2), Ps(-1, -2));
-            const A2 b12 = dif(Ps(-1, 2), Ps(1, -2)), b21 = dif(Ps(-2, 1), Ps(2, -1));
-            const A2 a22 = dif(Ps(2, 2), Ps(-2, -2)), b22 = dif(Ps(-2, 2), Ps(2, -2));
-            // rho differences over the 4 first-belt pairs (cross force).
-            const A2 r10 = dif(Rs(1, 0), Rs(-1, 0)), r01 = dif(Rs(0, 1), Rs(0, -1));
-            const A2 r11 = dif(Rs(1, 1), Rs(-1, -1)), q11 = dif(Rs(-1, 1), Rs(1, -1));
-            const A2 pc = Ps(0, 0);
-            const A2 rc = Rs(0, 0);
+            for (int i = 1; i < 9; ++i) v[i] = eq[i];
+        } else {
+#pragma unroll
+            for (int i = 1; i < 9; ++i) v[i] = v[i] + omega * (eq[i] - v[i]);
+        }
+        v[0] = rhod - (((v[1] + v[2]) + (v[3] + v[4])) + ((v[5] + v[6]) + (v[7] + v[8])));
+    }
 
-            A F[2][2];
-            auto force = [&](int s, A d10, A d01, A d11, A e11, A d20, A d02, A d21, A d12,
-                             A e12, A e21, A d22, A e22, A psi, A rho, A o10, A o01, A o11,
-                             A p11) {
-                const A Sx = c.K1[s] * d10 + c.K2[s] * (d11 - e11) + c.K4x2[s] * d20 +
-                             c.K5[s] * (A(2) * d21 + d12 - e12 - A(2) * e21) +
-                             c.K8x2[s] * (d22 - e22);
-                const A Sy = c.K1[s] * d01 + c.K2[s] * (d11 + e11) + c.K4x2[s] * d02 +
-                             c.K5[s] * (d21 + A(2) * d12 + A(2) * e12 + e21) +
-                             c.K8x2[s] * (d22 + e22);
-                const A Xx = c.X1 * o10 + c.X2 * (o11 - p11);
-                const A Xy = c.X1 * o01 + c.X2 * (o11 + p11);
-                F[s][0] = -psi * Sx - rho * Xx;
-                F[s][1] = -psi * Sy - rho * Xy;
-            };
-            force(0, a10.x, a01.x, a11.x, b11.x, a20.x, a02.x, a21.x, a12.x, b12.x, b21.x, a22.x,
-                  b22.x, pc.x, rc.x, r10.y, r01.y, r11.y, q11.y);
-            force(1, a10.y, a01.y, a11.y, b11.y, a20.y, a02.y, a21.y, a12.y, b12.y, b21.y, a22.y,
-                  b22.y, pc.y, rc.y, r10.x, r01.x, r11.x, q11.x);
-            if (c.body_F0 != 0.0) {
-                const A gy = (A)(c.body_F0 * sin(c.two_pi_over_ny * (double)y));
-                F[0][0] += rc.x * gy;
-                F[1][0] += rc.y * gy;
+    // Finish row y: forces from the LDS ring (slot sb holds row y-2), then
+    // collision + store (step), moment read-out or diagnostics.
+    __device__ void finish(int y, int sb, A* v)
+    {
+        const Coef<A>& c = I.c;
+        int sl[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sl[k] = sb + k >= NS ? sb + k - NS : sb + k;
+        auto Ps = [&](int dx, int dy) { return lpsi[sl[dy + 2]][t + dx]; };
+        auto Rs = [&](int dx, int dy) { return lrho[sl[dy + 2]][t + dx]; };
+        auto dif = [](A2 a, A2 b) { return A2{a.x - b.x, a.y - b.y}; };
+        // Psi differences over the 12 opposite pairs (both species)
+        const A2 a10 = dif(Ps(1, 0), Ps(-1, 0)), a01 = dif(Ps(0, 1), Ps(0, -1));
+        const A2 a11 = dif(Ps(1, 1), Ps(-1, -1)), b11 = dif(Ps(-1, 1), Ps(1, -1));
+        const A2 a20 = dif(Ps(2, 0), Ps(-2, 0)), a02 = dif(Ps(0, 2), Ps(0, -2));
+        const A2 a21 = dif(Ps(2, 1), Ps(-2, -1)), a12 = dif(Ps(1, 2), Ps(-1, -2));
+        const A2 b12 = dif(Ps(-1, 2), Ps(1, -2)), b21 = dif(Ps(-2, 1), Ps(2, -1));
+        const A2 a22 = dif(Ps(2, 2), Ps(-2, -2)), b22 = dif(Ps(-2, 2), Ps(2, -2));
+        // rho differences over the 4 first-belt pairs (cross force)
+        const A2 r10 = dif(Rs(1, 0), Rs(-1, 0)), r01 = dif(Rs(0, 1), Rs(0, -1));
+        const A2 r11 = dif(Rs(1, 1), Rs(-1, -1)), q11 = dif(Rs(-1, 1), Rs(1, -1));
+        const A2 pc = Ps(0, 0);
+        const A2 rc = Rs(0, 0);  // rhod of this row, staged two rows ago
+        const A rhod[2] = {rc.x, rc.y};
+        A rho[2] = {rc.x, rc.y};
+        if constexpr (DEV) {
+            rho[0] += c.rho_base[0];
+            rho[1] += c.rho_base[1];
+        }
+        A F[2][2];
+        auto force = [&](int s, A d10, A d01, A d11, A e11, A d20, A d02, A d21, A d12, A e12,
+                         A e21, A d22, A e22, A psi, A rho, A o10, A o01, A o11, A p11) {
+            const A Sx = c.K1[s] * d10 + c.K2[s] * (d11 - e11) + c.K4x2[s] * d20 +
+                         c.K5[s] * (A(2) * d21 + d12 - e12 - A(2) * e21) + c.K8x2[s] * (d22 - e22);
+            const A Sy = c.K1[s] * d01 + c.K2[s] * (d11 + e11) + c.K4x2[s] * d02 +
+                         c.K5[s] * (d21 + A(2) * d12 + A(2) * e12 + e21) + c.K8x2[s] * (d22 + e22);
+            const A Xx = c.X1 * o10 + c.X2 * (o11 - p11);
+            const A Xy = c.X1 * o01 + c.X2 * (o11 + p11);
+            F[s][0] = -psi * Sx - rho * Xx;
+            F[s][1] = -psi * Sy - rho * Xy;
+        };
+        force(0, a10.x, a01.x, a11.x, b11.x, a20.x, a02.x, a21.x, a12.x, b12.x, b21.x, a22.x,
+              b22.x, pc.x, rho[0], r10.y, r01.y, r11.y, q11.y);
+        force(1, a10.y, a01.y, a11.y, b11.y, a20.y, a02.y, a21.y, a12.y, b12.y, b21.y, a22.y,
+              b22.y, pc.y, rho[1], r10.x, r01.x, r11.x, q11.x);
+        if (c.body_F0 != 0.0) {  // uniform branch
+            const A gy = (A)c.body_F0 * (A)sin((A)c.two_pi_over_ny * (A)y);
+            F[0][0] += rho[0] * gy;
+            F[1][0] += rho[1] * gy;
+        }
+
+        A jx[2], jy[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const A* f = v + 9 * s;
+            jx[s] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+            jy[s] = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        }
+
+        if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG || MODE == M_READ) {
+            const A rt = rho[0] + rho[1];
+            const A mx = (jx[0] + A(0.5) * F[0][0]) + (jx[1] + A(0.5) * F[1][0]);
+            const A my = (jy[0] + A(0.5) * F[0][1]) + (jy[1] + A(0.5) * F[1][1]);
+            const A irt = rt > A(0) ? rcp<T>(rt) : A(0);
+            const A vx = mx * irt, vy = my * irt;
+            A sxy = A(0);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const A* f = v + 9 * s;
+                sxy -= c.hs[s] * ((f[5] - f[6]) + (f[7] - f[8]) - rho[s] * vx * vy);
             }
-
-            A rho[2], jx[2], jy[2];
-            moments<A>(P0, rho[0], jx[0], jy[0]);
-            moments<A>(P0 + 9, rho[1], jx[1], jy[1]);
-
-            if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG || MODE == M_READ) {
-                const A rt = rho[0] + rho[1];
-                const A mx = (jx[0] + A(0.5) * F[0][0]) + (jx[1] + A(0.5) * F[1][0]);
-                const A my = (jy[0] + A(0.5) * F[0][1]) + (jy[1] + A(0.5) * F[1][1]);
-                const A irt = rt > A(0) ? rcp<T>(rt) : A(0);
-                const A vx = mx * irt, vy = my * irt;
-                A sxy = A(0);
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const A* f = s ? P0 + 9 : P0;
-                    sxy -= c.hs[s] * ((f[5] - f[6]) + (f[7] - f[8]) - rho[s] * vx * vy);
-                }
-                if constexpr (MODE == M_READ) {
-                    const int64_t n = (int64_t)y * nx + xw;
-                    if (I.out[0]) I.out[0][n] = (double)rho[0];
-                    if (I.out[1]) I.out[1][n] = (double)rho[1];
-                    if (I.out[2]) I.out[2][n] = (double)vx;
-                    if (I.out[3]) I.out[3][n] = (double)vy;
-                    if (I.out[4]) I.out[4][n] = (double)sxy;
-                } else {
-                    acc[D_MASS_A] += (double)rho[0];
-                    acc[D_MASS_B] += (double)rho[1];
-                    acc[D_MOM_X] += (double)mx;
-                    acc[D_MOM_Y] += (double)my;
-                    acc[D_SXY] += (double)sxy;
-                    const bool ok = rho[0] > A(0) && rho[1] > A(0) && rho[0] < A(1e30) &&
-                                    rho[1] < A(1e30);
-                    acc[D_BAD] += ok ? 0.0 : 1.0;
-                }
+            if constexpr (MODE == M_READ) {
+                const int64_t n = (int64_t)y * nx + xw;
+                if (I.out[0]) I.out[0][n] = (double)rho[0];
+                if (I.out[1]) I.out[1][n] = (double)rho[1];
+                if (I.out[2]) I.out[2][n] = (double)vx;
+                if (I.out[3]) I.out[3][n] = (double)vy;
+                if (I.out[4]) I.out[4][n] = (double)sxy;
+            } else {
+                acc[D_MASS_A] += (double)rhod[0] + (double)c.rho_base[0] * DEV;
+                acc[D_MASS_B] += (double)rhod[1] + (double)c.rho_base[1] * DEV;
+                acc[D_MOM_X] += (double)mx;
+                acc[D_MOM_Y] += (double)my;
+                acc[D_SXY] += (double)sxy;
+                const bool ok = rho[0] > A(0) && rho[1] > A(0) && rho[0] < A(1e30) &&
+                                rho[1] < A(1e30);
+                acc[D_BAD] += ok ? 0.0 : 1.0;
             }
+        }
 
-            if constexpr (MODE == M_STEP || MODE == M_STEP_DIAG) {
-                // Shan-Chen velocity shift: common velocity weighted by
-                // rho_s/tau_s, species shift tau_s F_s / rho_s.
-                const A den = rho[0] * c.omega[0] + rho[1] * c.omega[1];
-                const A nmx = jx[0] * c.omega[0] + jx[1] * c.omega[1];
-                const A nmy = jy[0] * c.omega[0] + jy[1] * c.omega[1];
-                const A iden = den > A(0) ? rcp<T>(den) : A(0);
-                const A upx = nmx * iden, upy = nmy * iden;
-                const int ro = y + (WALLS ? 1 : 0);
-                const int64_t site = (int64_t)ro * g.pitch + xw;
+        if constexpr (MODE == M_STEP || MODE == M_STEP_DIAG) {
+            // Shan-Chen velocity shift: common velocity weighted by rho_s/tau_s,
+            // species shift tau_s F_s / rho_s.
+            const A den = rho[0] * c.omega[0] + rho[1] * c.omega[1];
+            const A nmx = jx[0] * c.omega[0] + jx[1] * c.omega[1];
+            const A nmy = jy[0] * c.omega[0] + jy[1] * c.omega[1];
+            const A iden = den > A(0) ? rcp<T>(den) : A(0);
+            const A upx = nmx * iden, upy = nmy * iden;
+            const int ro = y + (WALLS ? 1 : 0);
+            char* const rowb = foutb + (int64_t)ro * pitch_b;  // uniform
+            // Wall rows: a population that would leave the channel returns to
+            // its node reversed, minus 2 w_i rho (c_i.u_w)/c_s^2 (half-way
+            // bounce-back), written to the ghost row where the next pull of
+            // the reversed direction looks for it.  The outgoing value itself
+            // is never read and is not stored.
+            const bool bot = WALLS && y == 0, top = WALLS && y == ny - 1;
+            const A u6 = WALLS ? c.wall6u[top ? 1 : 0] : A(0);
+            char* const ghostb = foutb + (int64_t)(top ? ny + 1 : 0) * pitch_b;  // uniform
+            double mxw = 0.0, myw = 0.0;
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    A* f = s ? P0 + 9 : P0;
-                    const A ir = rho[s] > A(0) ? c.tau[s] * rcp<T>(rho[s]) : A(0);
-                    const A uex = upx + F[s][0] * ir, uey = upy + F[s][1] * ir;
-                    bgk<A>(f, rho[s], uex, uey, c.omega[s]);
+            for (int s = 0; s < 2; ++s) {
+                A* f = v + 9 * s;
+                const A ir = rho[s] > A(0) ? c.tau[s] * rcp<T>(rho[s]) : A(0);
+                const A uex = upx + F[s][0] * ir, uey = upy + F[s][1] * ir;
+                bgk(f, rho[s], rhod[s], uex, uey, c.omega[s], c.tau1[s] != 0);
+                const A corr = A(W2) * rho[s] * u6;  // diagonal Ladd term; axis term is 0
+                [[maybe_unused]] A qsum = A(0);
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        st<T>(fout + (int64_t)(s * 9 + i) * g.plane + site, f[i], c.base[s][i]);
-                }
-                if constexpr (WALLS) {
-                    // Half-way bounce-back: a population leaving the channel
-                    // returns to its node reversed, minus 2 w_i rho (c_i.u_w)/c_s^2.
-                    // It is written to the ghost row where the next pull of the
-                    // reversed direction looks for it.
-                    if (y == 0 || y == ny - 1) {
-                        const bool top = y == ny - 1;
-                        const A u6 = c.wall6u[top ? 1 : 0];
-                        const int grow = top ? ny + 1 : 0;
-                        const int64_t gb = (int64_t)grow * g.pitch;
-                        // outgoing i -> stored as j = opp(i): bottom (4->2, 7->5, 8->6),
-                        // top (2->4, 5->7, 6->8); column x + c_ix.
-                        const int io0 = top ? 2 : 4, io1 = top ? 5 : 7, io2 = top ? 6 : 8;
-                        const int jo0 = top ? 4 : 2, jo1 = top ? 7 : 5, jo2 = top ? 8 : 6;
-                        const int cx1 = top ? 1 : -1;  // c_x of io1; io2 has -cx1
-                        const int col1 = top ? xp : xm, col2 = top ? xm : xp;
-                        double mxw = 0.0, myw = 0.0;
-#pragma unroll
-                        for (int s = 0; s < 2; ++s) {
-                            const A* f = s ? P0 + 9 : P0;
-                            const A corr = A(W2) * rho[s] * u6;
-                            const A v0 = f[io0];
-                            const A v1 = f[io1] - A(cx1) * corr;
-                            const A v2 = f[io2] + A(cx1) * corr;
-                            st<T>(fout + (int64_t)(s * 9 + jo0) * g.plane + gb + xw, v0,
-                                  c.base[s][jo0]);
-                            st<T>(fout + (int64_t)(s * 9 + jo1) * g.plane + gb + col1, v1,
-                                  c.base[s][jo1]);
-                            st<T>(fout + (int64_t)(s * 9 + jo2) * g.plane + gb + col2, v2,
-                                  c.base[s][jo2]);
-                            // momentum received by the wall: c_i (f*_i + reflected)
-                            const double cy = top ? 1.0 : -1.0;
-                            mxw += (double)cx1 * ((double)f[io1] + (double)v1) -
-                                   (double)cx1 * ((double)f[io2] + (double)v2);
-                            myw += cy * (((double)f[io0] + (double)v0) +
-                                         ((double)f[io1] + (double)v1) +
-                                         ((double)f[io2] + (double)v2));
-                        }
-                        double* wa = I.wall_acc + (top ? 2 : 0) * (int64_t)nx;
-                        wa[xw] += mxw;
-                        wa[nx + xw] += myw;
+                for (int i = 1; i < 9; ++i) {
+                    const bool out = (bot && CY_[i] < 0) || (top && CY_[i] > 0);
+                    A val = f[i];
+                    S* dst = (S*)(rowb + (int64_t)(s * 9 + i) * plane_b + cw);
+                    if (out) {
+                        val = f[i] - A(CX_[i]) * corr;
+                        const uint32_t col = CX_[i] > 0 ? cp : CX_[i] < 0 ? cm : cw;
+                        dst = (S*)(ghostb + (int64_t)(s * 9 + OPP_[i]) * plane_b + col);
+                        mxw += (double)CX_[i] * ((double)f[i] + (double)val);
+                        myw += (double)CY_[i] * ((double)f[i] + (double)val);
+                        if constexpr (DEV)  // the reference populations' share
+                            myw += (double)CY_[i] * 2.0 * (double)c.rho_base[s] *
+                                   (CX_[i] == 0 ? W1 : W2);
+                    }
+                    if constexpr (DEV) {
+                        const _Float16 h = (_Float16)val;
+                        *dst = h;
+                        qsum += (float)h;  // exact: sum of binary16 values
+                    } else {
+                        *dst = (S)val;
                     }
                 }
+                S* d0 = (S*)(rowb + (int64_t)(s * 9) * plane_b + cw);
+                if constexpr (DEV) {
+                    // The rest population absorbs the rounding of the other
+                    // eight deviations and is itself rounded stochastically
+                    // (unbiased): the site's stored mass is rho_s up to one
+                    // zero-mean rounding.
+                    const float h0 = rhod[s] - qsum;
+                    const uint32_t r = hash32(
+                        I.seed ^ (uint32_t)(((uint32_t)y * (uint32_t)nx + (uint32_t)xw) * 2u + s));
+                    typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+                    h2_t hv = {(_Float16)0, (_Float16)0};
+                    hv = __builtin_amdgcn_cvt_sr_f16_f32(hv, h0, r, false);
+                    *d0 = hv[0];
+                } else {
+                    *d0 = (S)f[0];
+                }
+            }
+            if constexpr (WALLS) {
+                if (bot || top) {
+                    double* wa = I.wall_acc + (top ? 2 : 0) * (int64_t)nx;
+                    wa[xw] += mxw;
+                    wa[nx + xw] += myw;
+                }
             }
         }
-        // rotate the register rows
-#pragma unroll
-        for (int k = 0; k < 18; ++k) {
-            P0[k] = P1[k];
-            P1[k] = P2[k];
+    }
+
+    // One sweep iteration: stage row y+2 (buffer PC), barrier, start the
+    // loads of row y+3 (into PD, or the raw buffer R for FP16), finish row y
+    // (PA).  FP64 loads row y+2 here instead (no prefetch).
+    __device__ void iterate(int y, int& sb, int y1, A* PA, A* PC, A* PD)
+    {
+        const int snew = sb + 4 >= 6 ? sb - 2 : sb + 4;
+        if constexpr (!PF) load_into(y + 2, PC);
+        if constexpr (DEV) convert(PC);
+        stage(snew, PC);
+        __syncthreads();
+        if constexpr (PF) {
+            if (y + 1 < y1) {
+                if constexpr (DEV)
+                    load(y + 3);
+                else
+                    load_into(y + 3, PD);
+            }
         }
+        if (own) finish(y, sb, PA);
         sb = sb == 5 ? 0 : sb + 1;
     }
-}
+
+    __device__ void run(int chunk)
+    {
+        const int y0 = chunk * I.H;
+        const int y1 = min(y0 + I.H, ny);
+        A P0[18], P1[18], P2[18];
+        // prologue: rows y0-2 .. y0+1 in slots 0..3; keep rows y0, y0+1
+        auto pro = [&](int r, int slot, A* v) {
+            load(r);
+            convert(v);
+            stage(slot, v);
+        };
+        pro(y0 - 2, 0, P2);
+        pro(y0 - 1, 1, P2);
+        pro(y0, 2, P0);
+        pro(y0 + 1, 3, P1);
+        int sb = 0;  // slot of row y-2
+        int y = y0;
+        if constexpr (PF && !DEV) {
+            // four row buffers rotate (row y, y+1, y+2 resident, y+3 loading)
+            A P3[18];
+            load_into(y0 + 2, P2);
+            for (; y + 4 <= y1; y += 4) {
+                iterate(y, sb, y1, P0, P2, P3);
+                iterate(y + 1, sb, y1, P1, P3, P0);
+                iterate(y + 2, sb, y1, P2, P0, P1);
+                iterate(y + 3, sb, y1, P3, P1, P2);
+            }
+            if (y < y1) iterate(y, sb, y1, P0, P2, P3);
+            if (y + 1 < y1) iterate(y + 1, sb, y1, P1, P3, P0);
+            if (y + 2 < y1) iterate(y + 2, sb, y1, P2, P0, P1);
+        } else {
+            // three row buffers (FP16: raw prefetch buffer R besides)
+            if constexpr (PF) load(y0 + 2);
+            for (; y + 3 <= y1; y += 3) {
+                iterate(y, sb, y1, P0, P2, nullptr);
+                iterate(y + 1, sb, y1, P1, P0, nullptr);
+                iterate(y + 2, sb, y1, P2, P1, nullptr);
+            }
+            if (y < y1) iterate(y, sb, y1, P0, P2, nullptr);
+            if (y + 1 < y1) iterate(y + 1, sb, y1, P1, P0, nullptr);
+        }
+    }
+};
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
 // give each XCD a contiguous range of logical tiles.
@@ -397,11 +521,49 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
     __shared__ typename T::A2 lrho[6][64 * CW];
     __shared__ double red[CW][NDIAG];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int strip = b / I.nchunks, chunk = b - (b / I.nchunks) * I.nchunks;
+    const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    sweep<T, CW, WALLS, MODE>(I, strip, chunk, lpsi, lrho, acc);
+    Sweep<T, CW, WALLS, MODE> sw(I, strip, lpsi, lrho, acc);
+    sw.run(chunk);
     if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
         block_reduce<CW>(acc, red, I.partials + (int64_t)b * NDIAG);
+}
+
+// Tile mode for lattices too small to fill the chip with sweeps: RW waves
+// stacked along y, one row each.  Wave w stages its own row y0+w (and keeps
+// its populations in registers); waves 0..3 also stage the four halo rows
+// y0-2, y0-1, y0+RW, y0+RW+1; one barrier; every wave finishes its row.  The
+// dependency chain per workgroup is one row instead of H+4 rows.
+template <class T, int RW, bool WALLS, int MODE>
+__global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typename T::A> I)
+{
+    static_assert(RW >= 4, "four waves stage the halo rows");
+    using A = typename T::A;
+    __shared__ typename T::A2 lpsi[RW + 4][64];
+    __shared__ typename T::A2 lrho[RW + 4][64];
+    __shared__ double red[RW][NDIAG];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    Sweep<T, 1, WALLS, MODE, RW + 4> sw(I, strip, lpsi, lrho, acc);
+    const int w = threadIdx.x >> 6;  // uniform per wave
+    const int y0 = chunk * RW;
+    A P[18];
+    sw.load(y0 + w);
+    sw.convert(P);
+    if (w < 4) {
+        A Q[18];
+        const int hr = w < 2 ? y0 - 2 + w : y0 + RW + (w - 2);
+        const int hs = w < 2 ? w : RW + w;
+        sw.load(hr);
+        sw.convert(Q);
+        sw.stage(hs, Q);
+    }
+    sw.stage(w + 2, P);
+    __syncthreads();
+    if (sw.own && y0 + w < sw.ny) sw.finish(y0 + w, w, P);
+    if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
+        block_reduce<RW>(acc, red, I.partials + (int64_t)b * NDIAG);
 }
 
 // Fixed-order FP64 reduction of per-block partials: deterministic.
@@ -476,12 +638,23 @@ __global__ __launch_bounds__(256) void init_kernel(Inst<typename T::S, typename 
                 ys += 1;  // ghost row 0 / ny+1 hold sources outside the channel
             else
                 ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-            st<T>(I.fout + (int64_t)(s * 9 + i) * g.plane + (int64_t)ys * g.pitch + xs,
-                  (typename T::A)feq, I.c.base[s][i]);
+            typename T::S* dst = I.fout + (int64_t)(s * 9 + i) * g.plane + (int64_t)ys * g.pitch + xs;
+            if constexpr (std::is_same<T, TF16>::value)  // deviation from w_i rho_ref
+                *dst = (_Float16)(float)(feq - w[i] * (double)I.c.rho_base[s]);
+            else
+                *dst = (typename T::S)feq;
         }
 }
 
 // ---------------------------------------------------------------- launchers
+
+template <class T, int RW, bool WALLS, int MODE>
+static hipError_t go_tile(const void* inst, int nb, hipStream_t st)
+{
+    const auto& I = *static_cast<const Inst<typename T::S, typename T::A>*>(inst);
+    hipLaunchKernelGGL((tile_kernel<T, RW, WALLS, MODE>), dim3(nb), dim3(64 * RW), 0, st, I);
+    return hipGetLastError();
+}
 
 template <class T, int CW, bool WALLS, int MODE>
 static hipError_t go(const void* inst, int nb, hipStream_t st)
@@ -503,9 +676,26 @@ static hipError_t go_mode(int mode, const void* inst, int nb, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
+template <class T, bool WALLS>
+static hipError_t go_stacked(int rw, int mode, const void* inst, int nb, hipStream_t st)
+{
+    if (mode != M_STEP && mode != M_STEP_DIAG) return hipErrorInvalidValue;
+    const bool d = mode == M_STEP_DIAG;
+    switch (rw) {
+    case 4: return d ? go_tile<T, 4, WALLS, M_STEP_DIAG>(inst, nb, st)
+                     : go_tile<T, 4, WALLS, M_STEP>(inst, nb, st);
+    case 8: return d ? go_tile<T, 8, WALLS, M_STEP_DIAG>(inst, nb, st)
+                     : go_tile<T, 8, WALLS, M_STEP>(inst, nb, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <class T>
 static hipError_t go_cw(int cw, int walls, int mode, const void* inst, int nb, hipStream_t st)
 {
+    if (cw < 0)  // stacked tile mode with -cw waves
+        return walls ? go_stacked<T, true>(-cw, mode, inst, nb, st)
+                     : go_stacked<T, false>(-cw, mode, inst, nb, st);
     switch (cw) {
     case 1: return walls ? go_mode<T, 1, true>(mode, inst, nb, st)
                          : go_mode<T, 1, false>(mode, inst, nb, st);

@@ -62,7 +62,7 @@ class Diag(ctypes.Structure):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("stacked", ctypes.c_int32)]
 
 
 class SclbmError(RuntimeError):
@@ -72,6 +72,10 @@ class SclbmError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+    # first makes libsclbm.so bind to that same runtime, so device buffers and
+    # streams from torch are valid in the library.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_0807_4471_amd.build` (no fallback exists)")
@@ -223,14 +227,14 @@ class Simulation:
         check(lib.sclbm_time(self._h, ctypes.byref(v)), "time")
         return v.value
 
-    def set_tiling(self, tile_x: int, tile_y: int, waves: int):
-        t = Tiling(int(tile_x), int(tile_y), int(waves), 0)
+    def set_tiling(self, tile_x: int, tile_y: int, waves: int, stacked: int = 0):
+        t = Tiling(int(tile_x), int(tile_y), int(waves), int(stacked))
         check(lib.sclbm_set_tiling(self._h, ctypes.byref(t)), "set_tiling")
 
     def get_tiling(self):
         t = Tiling()
         check(lib.sclbm_get_tiling(self._h, ctypes.byref(t)), "get_tiling")
-        return (t.tile_x, t.tile_y, t.waves)
+        return (t.tile_x, t.tile_y, t.waves, t.stacked)
 
     # ------------------------------------------------------------------ read
     def moments_device(self, stream=None):

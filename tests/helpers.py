@@ -1,0 +1,65 @@
+"""Shared helpers for the GPU tests: run the same seeded input through the
+HIP library (via its C ABI binding) and through the CPU oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_0807_4471_amd import inputs
+
+WORKLOAD = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
+_ORACLE_KEYS = ("tau", "Ga", "Gr", "Gx", "rho0", "psi_amp", "wall_u", "body_F0")
+
+
+def banner(msg: str):
+    print(f"[case] {msg}", flush=True)
+
+
+def gpu_run(nx, ny, steps, rho=None, ux=None, uy=None, seed=1, tiling=None, **kw):
+    """Returns (Simulation, moments dict) after `steps` steps."""
+    from paper_0807_4471_amd import sclbm
+    sim = sclbm.Simulation(nx, ny, **kw)
+    if tiling is not None:
+        sim.set_tiling(*tiling)
+    if rho is None:
+        rho = inputs.random_densities(nx, ny, seed)
+    sim.init_fields(rho, ux, uy)
+    sim.step(steps)
+    return sim, sim.moments()
+
+
+def oracle_run(nx, ny, steps, rho=None, ux=None, uy=None, seed=1, boundary="periodic", **kw):
+    """Returns (params, f, (rho, ux, uy)) of the FP64 oracle."""
+    okw = {k: v for k, v in kw.items() if k in _ORACLE_KEYS}
+    p = oracle.Params(nx=nx, ny=ny, walls=(boundary == "walls"), **okw)
+    if rho is None:
+        rho = inputs.random_densities(nx, ny, seed)
+    f = oracle.init(p, rho, ux, uy)
+    oracle.run(p, f, steps)
+    return p, f, oracle.moments(p, f)
+
+
+def max_err(m: dict, ref) -> dict:
+    r, ux, uy = ref
+    return {
+        "rho": max(np.abs(m["rhoA"] - r[0]).max(), np.abs(m["rhoB"] - r[1]).max()),
+        "u": max(np.abs(m["ux"] - ux).max(), np.abs(m["uy"] - uy).max()),
+    }
+
+
+def structure_factor(phi: np.ndarray):
+    """Radially averaged S(k) of phi - <phi> on integer |k| shells; returns
+    (k_shell, S) with S normalised by the number of sites."""
+    ny, nx = phi.shape
+    F = np.fft.fft2(phi - phi.mean())
+    S = (np.abs(F) ** 2) / (nx * ny)
+    ky = np.fft.fftfreq(ny) * ny
+    kx = np.fft.fftfreq(nx) * nx
+    K = np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)
+    shell = np.rint(K).astype(int)
+    nsh = shell.max() + 1
+    tot = np.bincount(shell.ravel(), S.ravel(), nsh)
+    cnt = np.bincount(shell.ravel(), None, nsh)
+    ks = np.arange(nsh)
+    ok = cnt > 0
+    return ks[ok][1:], (tot[ok] / cnt[ok])[1:]

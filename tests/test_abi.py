@@ -1,0 +1,104 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/sclbm.h declares, and rejects invalid input before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sclbm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0807_4471_amd import sclbm
+    return sclbm
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sclbm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared()
+    assert len(names) >= 20
+    raw = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_version_and_strerror(L):
+    assert L.lib.sclbm_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.strerror(code) and L.strerror(code) != "unknown status"
+    assert L.strerror(-99) == "unknown status"
+
+
+def test_state_bytes_scaling(L):
+    a = L.state_bytes(L.make_desc(512, 512, storage="f32"))
+    b = L.state_bytes(L.make_desc(512, 512, storage="f16dev"))
+    c = L.state_bytes(L.make_desc(512, 512, storage="f64"))
+    pop32 = 2 * 18 * 512 * 512 * 4
+    assert pop32 <= a < pop32 * 1.05
+    assert b < a < c
+    w = L.state_bytes(L.make_desc(512, 512, storage="f32", boundary="walls"))
+    assert w > a          # two ghost rows
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-1), dict(nx=70000), dict(tau=(0.5, 1.0)), dict(tau=(1.0, float("nan"))),
+    dict(rho0=0.0), dict(psi_amp=-1.0), dict(Gx=float("inf")), dict(diag_every=-2),
+    dict(boundary=7), dict(storage=9), dict(boundary="walls", ny=1),
+    dict(storage="f16dev", rho_ref=(float("nan"), 0.7)),
+])
+def test_invalid_descriptors(L, bad):
+    kw = dict(nx=32, ny=32)
+    kw.update(bad)
+    d = L.make_desc(**kw)
+    assert L.state_bytes(d) == 0
+    h = ctypes.c_void_p()
+    rc = L.lib.sclbm_bind(ctypes.byref(d), ctypes.c_void_p(1 << 20), 1 << 30, ctypes.byref(h))
+    assert rc == L.EINVAL and not h.value
+    assert L.last_error()
+
+
+def test_bind_errors_and_state(L):
+    d = L.make_desc(100, 60, storage="f32")
+    need = L.state_bytes(d)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)          # never dereferenced by bind
+    assert L.lib.sclbm_bind(ctypes.byref(d), fake, need - 1, ctypes.byref(h)) == L.ESIZE
+    assert L.lib.sclbm_bind(ctypes.byref(d), None, need, ctypes.byref(h)) == L.EINVAL
+    assert L.lib.sclbm_bind(ctypes.byref(d), ctypes.c_void_p((1 << 20) + 8), need,
+                            ctypes.byref(h)) == L.EINVAL
+    assert L.lib.sclbm_bind(ctypes.byref(d), fake, need, None) == L.EINVAL
+    assert L.lib.sclbm_bind(ctypes.byref(d), fake, need, ctypes.byref(h)) == L.OK
+    try:
+        # not initialised: no device work may be enqueued
+        assert L.lib.sclbm_step(h, 1, None) == L.ESTATE
+        assert L.lib.sclbm_read_moments(h, None, None, None, None, None, None) == L.ESTATE
+        assert L.lib.sclbm_step(h, -1, None) in (L.ESTATE, L.EINVAL)
+        t = L.Tiling()
+        assert L.lib.sclbm_get_tiling(h, ctypes.byref(t)) == L.OK
+        assert (t.stacked == 0 and t.waves in (1, 2, 4) and t.tile_x <= 64 * t.waves - 4) or \
+            (t.stacked == 1 and t.waves in (4, 8) and t.tile_x <= 60)
+        for bad in [(61, 8, 1, 0), (60, 8, 3, 0), (20, 8, 1, 0), (60, 3, 1, 0), (253, 8, 4, 0),
+                    (60, 8, 4, 1), (61, 8, 8, 1), (60, 8, 2, 1), (60, 8, 8, 2)]:
+            tb = L.Tiling(*bad)
+            assert L.lib.sclbm_set_tiling(h, ctypes.byref(tb)) == L.EINVAL, bad
+        ok = L.Tiling(100, 8, 2, 0)
+        assert L.lib.sclbm_set_tiling(h, ctypes.byref(ok)) == L.OK
+        assert L.lib.sclbm_get_tiling(h, ctypes.byref(t)) == L.OK
+        assert (t.tile_x, t.tile_y, t.waves, t.stacked) == (100, 8, 2, 0)
+        ok = L.Tiling(50, 8, 8, 1)
+        assert L.lib.sclbm_set_tiling(h, ctypes.byref(ok)) == L.OK
+        v = ctypes.c_int64(-5)
+        assert L.lib.sclbm_time(h, ctypes.byref(v)) == L.OK
+        assert L.lib.sclbm_checkpoint_bytes(h) > 0
+        assert L.lib.sclbm_restore(h, ctypes.create_string_buffer(8), 8, None) == L.ESIZE
+    finally:
+        assert L.lib.sclbm_release(h) == L.OK
+    assert L.lib.sclbm_release(None) == L.OK

@@ -1,0 +1,152 @@
+"""Invariants of the HIP path that hold exactly (bit for bit) or to FP64
+rounding, at sizes the oracle could not follow for long."""
+import numpy as np
+import pytest
+
+from helpers import WORKLOAD, banner
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(nx, ny, storage, **kw):
+    from paper_0807_4471_amd import sclbm
+    return sclbm.Simulation(nx, ny, storage=storage, **dict(WORKLOAD, **kw))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_tiling_does_not_change_results(storage):
+    """Every tiling (strip width, chunk height, waves per workgroup) gives the
+    same bits: halos and ragged tails are handled exactly."""
+    nx, ny = 200, 90
+    banner(f"{storage} tiling invariance {nx}x{ny}")
+    ref = None
+    for tl in [(60, 8, 1), (33, 17, 1), (124, 8, 2), (100, 45, 2), (200, 90, 4), (252, 8, 4),
+               (71, 30, 4), (60, 4, 1), (60, 8, 8, 1), (41, 4, 4, 1), (50, 8, 8, 1)]:
+        s = _sim(nx, ny, storage)
+        s.set_tiling(*tl)
+        s.init_random(7)
+        s.step(25)
+        m = s.moments()
+        if ref is None:
+            ref = m
+        else:
+            for k in ("rhoA", "rhoB", "ux", "uy"):
+                assert np.array_equal(m[k], ref[k]), (tl, k)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_translation_invariance(storage):
+    from paper_0807_4471_amd import inputs
+    nx, ny = 96, 80
+    banner(f"{storage} translation invariance")
+    rho = inputs.random_densities(nx, ny, 9)
+    a = _sim(nx, ny, storage)
+    a.init_fields(rho)
+    b = _sim(nx, ny, storage)
+    b.init_fields(np.roll(rho, (13, -29), axis=(1, 2)).copy())
+    a.step(40)
+    b.step(40)
+    ma, mb = a.moments(), b.moments()
+    assert np.array_equal(np.roll(ma["rhoA"], (13, -29), axis=(0, 1)), mb["rhoA"])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("boundary", ["periodic", "walls"])
+def test_checkpoint_restore_bitwise(storage, boundary):
+    nx, ny = 90, 50
+    banner(f"{storage} {boundary} checkpoint/restore")
+    kw = dict(boundary=boundary, wall_u=(0.0, 0.05))
+    a = _sim(nx, ny, storage, **kw)
+    a.init_random(3)
+    a.step(30)
+    ck = a.checkpoint()
+    a.step(25)
+    b = _sim(nx, ny, storage, **kw)
+    b.restore(ck)
+    assert b.t == 30
+    b.step(25)
+    ma, mb = a.moments(), b.moments()
+    for k in ("rhoA", "rhoB", "ux", "uy"):
+        assert np.array_equal(ma[k], mb[k]), k
+
+
+def test_determinism_and_stream_use():
+    import torch
+    banner("f32 repeatability on a side stream")
+    outs = []
+    for use_side in (False, True):
+        s = _sim(300, 200, "f32")
+        st = torch.cuda.Stream() if use_side else None
+        s.init_random(11, stream=st)
+        s.step(60, stream=st)
+        if st is not None:
+            st.synchronize()
+        outs.append(s.moments())
+    assert np.array_equal(outs[0]["rhoA"], outs[1]["rhoA"])
+
+
+# Mass is conserved exactly in real arithmetic; per step each collision and
+# each stored population adds at most a few units of rounding.  Bounds for
+# 2000 steps: FP64 2000 * 4 * 2^-53 ~ 1e-12; FP32 2000 * 4 * 2^-24 ~ 5e-4
+# (worst case, fully systematic rounding); FP16 deviations round
+# independently (RNE): 5 sigma of a random walk of 2000 * 18 * 65536
+# roundings of ulp <= 2^-12 gives ~1e-3.
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 5e-4), ("f16dev", 1e-3)])
+@pytest.mark.parametrize("boundary", ["periodic", "walls"])
+def test_mass_conservation(storage, tol, boundary):
+    """Per-species mass (FP64 totals on the GPU) after 2000 steps on 256x256."""
+    banner(f"{storage} {boundary} mass conservation 256x256")
+    s = _sim(256, 256, storage, boundary=boundary, wall_u=(0.0, 0.1))
+    s.init_random(5)
+    d0 = s.diagnostics()
+    s.step(2000)
+    d1 = s.diagnostics()
+    drift = np.abs(d1["mass"] - d0["mass"]) / d0["mass"]
+    print(f"  mass drift {storage} {boundary}: {drift}", flush=True)
+    assert np.all(drift < tol), drift
+    assert d1["bad_sites"] == 0
+    if boundary == "periodic":
+        assert np.all(np.abs(d1["mom"]) < tol * d0["mass"].sum())
+
+
+def test_nonfinite_is_reported():
+    """A NaN planted in one population through the caller's buffer is found by
+    the diagnostics (status ENONFINITE), without faulting anything."""
+    import torch
+    from paper_0807_4471_amd import sclbm
+    banner("non-finite detection")
+    s = _sim(64, 64, "f32")
+    s.init_random(1)
+    s.step(4)
+    # after an even number of steps the state is the first population copy,
+    # which starts at offset 0 of the state buffer
+    view = s.buf[: 64 * 64 * 4].view(torch.float32)
+    view[100] = float("nan")
+    torch.cuda.synchronize()
+    d = s.diagnostics()
+    assert d["bad_sites"] >= 1
+    with pytest.raises(sclbm.SclbmError) as ei:
+        s.diagnostics(raise_nonfinite=True)
+    assert ei.value.status == sclbm.ENONFINITE
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16dev", 1.5e-3)])
+def test_long_run_mass_drift(storage, tol):
+    """20000 steps on 128x128: the collision conserves mass to one rounding
+    per site (rest population as remainder), so the drift stays far below
+    the 7.4e-9 per step that FP32-rounded weights would cause (1.5e-4 here).
+    What is left for FP32 is a small rounding bias, measured at ~3e-10 per
+    step; the bound allows 1e-9 per step.  For FP16 deviations the rest
+    population absorbs the other roundings and is rounded stochastically,
+    so the drift is a random walk of 20000 * 16384 * 2 zero-mean roundings
+    of size <= 2^-12: 5 sigma = 1.5e-3 relative (round-to-nearest gave a
+    biased 4.6e-3)."""
+    banner(f"{storage} 20000-step mass drift 128x128")
+    s = _sim(128, 128, storage)
+    s.init_random(2)
+    d0 = s.diagnostics()
+    s.step(20000)
+    d1 = s.diagnostics()
+    drift = np.abs(d1["mass"] - d0["mass"]) / d0["mass"]
+    print(f"  long-run mass drift {storage}: {drift}", flush=True)
+    assert np.all(drift < tol), drift

@@ -1,0 +1,161 @@
+"""FP64 parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: the workload's 64x64 FP64 case must match to <= 1e-10 max-abs density
+after 1000 steps.  Shorter runs are held to 1e-12 (FP64 rounding of a few
+hundred operations per value, amplified at most ~1e3x by the demixing
+transient; measured ~1e-15 per step).  Sizes span several strips and
+chunks with ragged tails, odd shapes, lattices narrower than one strip and
+shorter than the stencil.
+"""
+import numpy as np
+import pytest
+
+from helpers import WORKLOAD, banner, gpu_run, max_err, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("nx,ny,steps", [
+    (1, 1, 3), (2, 3, 5), (5, 5, 10), (8, 8, 20), (9, 7, 20), (13, 21, 25),
+    (64, 1, 10), (1, 40, 10), (70, 37, 30), (125, 19, 15), (300, 45, 8),
+])
+def test_small_and_ragged_f64(nx, ny, steps):
+    banner(f"f64 periodic {nx}x{ny} steps={steps}")
+    _, m = gpu_run(nx, ny, steps, storage="f64", **WORKLOAD)
+    _, _, ref = oracle_run(nx, ny, steps, **WORKLOAD)
+    e = max_err(m, ref)
+    assert e["rho"] <= 1e-12 and e["u"] <= 1e-12, e
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_workload_64_f64_1000_steps(seed):
+    """64x64, FP64, tau = 1, A = rho0 = 0.7, the caption couplings, 1000 steps."""
+    banner(f"f64 64x64 1000 steps seed={seed}")
+    _, m = gpu_run(64, 64, 1000, seed=seed, storage="f64", **WORKLOAD)
+    _, _, ref = oracle_run(64, 64, 1000, seed=seed, **WORKLOAD)
+    e = max_err(m, ref)
+    assert e["rho"] <= 1e-10, e
+    assert ref[0].shape == (2, 64, 64)
+
+
+@pytest.mark.parametrize("variant", ["sqrt_amp", "text_couplings", "unequal_tau", "gx_only"])
+def test_parameter_variants_f64(variant):
+    kw = dict(WORKLOAD)
+    if variant == "sqrt_amp":
+        kw["psi_amp"] = 0.7 ** 0.5
+    elif variant == "text_couplings":
+        kw.update(Ga=(-12.55, -11.70), Gr=(11.80, 10.95))
+    elif variant == "unequal_tau":
+        kw["tau"] = (0.8, 1.25)
+    else:
+        kw.update(Ga=(0.0, 0.0), Gr=(0.0, 0.0), Gx=1.2)
+    banner(f"f64 variant {variant}")
+    _, m = gpu_run(48, 40, 60, storage="f64", **kw)
+    _, _, ref = oracle_run(48, 40, 60, **kw)
+    e = max_err(m, ref)
+    assert e["rho"] <= 1e-12 and e["u"] <= 1e-12, e
+
+
+@pytest.mark.parametrize("nx,ny,uw", [(40, 24, (0.0, 0.05)), (67, 9, (-0.03, 0.1)),
+                                      (5, 2, (0.02, 0.0)), (130, 50, (0.0, 0.1))])
+def test_walls_f64(nx, ny, uw):
+    banner(f"f64 walls {nx}x{ny} wall_u={uw}")
+    sim, m = gpu_run(nx, ny, 120, storage="f64", boundary="walls", wall_u=uw, **WORKLOAD)
+    p, f, ref = oracle_run(nx, ny, 120, boundary="walls", wall_u=uw, **WORKLOAD)
+    e = max_err(m, ref)
+    assert e["rho"] <= 1e-11 and e["u"] <= 1e-12, e
+
+
+def test_wall_momentum_f64():
+    import oracle
+    from paper_0807_4471_amd import inputs, sclbm
+    nx, ny, uw = 36, 20, (0.0, 0.08)
+    banner("f64 wall momentum exchange")
+    rho = inputs.random_densities(nx, ny, 4)
+    sim = sclbm.Simulation(nx, ny, storage="f64", boundary="walls", wall_u=uw, **WORKLOAD)
+    sim.init_fields(rho)
+    sim.step(50)
+    sim.reset_wall_accum()
+    sim.step(30)
+    d = sim.diagnostics()
+    p = oracle.Params(nx=nx, ny=ny, walls=True, wall_u=uw, **WORKLOAD)
+    f = oracle.init(p, rho)
+    oracle.run(p, f, 50)
+    wm = np.zeros((2, 2))
+    oracle.run(p, f, 30, wm)
+    assert d["wall_steps"] == 30
+    np.testing.assert_allclose(d["wall_mom"], wm, rtol=1e-9, atol=1e-12)
+
+
+def test_body_force_f64():
+    kw = dict(WORKLOAD, body_F0=2e-4)
+    banner("f64 Kolmogorov body force")
+    _, m = gpu_run(32, 48, 80, storage="f64", **kw)
+    _, _, ref = oracle_run(32, 48, 80, **kw)
+    e = max_err(m, ref)
+    assert e["rho"] <= 1e-12 and e["u"] <= 1e-12, e
+
+
+def test_moments_and_stress_f64():
+    import oracle
+    banner("f64 moments + sigma_xy + totals")
+    sim, m = gpu_run(50, 30, 40, storage="f64", tau=(0.9, 1.1), **WORKLOAD)
+    p, f, ref = oracle_run(50, 30, 40, tau=(0.9, 1.1), **WORKLOAD)
+    ux_row, sxy_row = oracle.row_profiles(p, f)
+    np.testing.assert_allclose(m["sxy"].mean(axis=1), sxy_row, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(m["ux"].mean(axis=1), ux_row, rtol=0, atol=1e-13)
+    d = sim.diagnostics()
+    tot = oracle.totals(p, f)
+    np.testing.assert_allclose(d["mass"], tot["mass"], rtol=1e-13)
+    np.testing.assert_allclose(d["mom"], tot["mom"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(d["sxy"], tot["sxy"], rtol=0, atol=1e-11)
+    assert d["bad_sites"] == tot["bad"] == 0
+    assert d["step"] == 40
+
+
+def test_fused_diagnostics_f64():
+    from paper_0807_4471_amd import inputs, sclbm
+    import oracle
+    banner("f64 fused diagnostics every 7 steps")
+    rho = inputs.random_densities(33, 29, 6)
+    sim = sclbm.Simulation(33, 29, storage="f64", diag_every=7, **WORKLOAD)
+    sim.init_fields(rho)
+    sim.step(23)
+    d = sim.fused_diagnostics()
+    assert d["step"] == 21
+    p = oracle.Params(nx=33, ny=29, **WORKLOAD)
+    f = oracle.init(p, rho)
+    oracle.run(p, f, 21)
+    tot = oracle.totals(p, f)
+    np.testing.assert_allclose(d["mass"], tot["mass"], rtol=1e-13)
+    np.testing.assert_allclose(d["mom"], tot["mom"], rtol=0, atol=1e-12)
+
+
+def test_init_random_matches_input_generator():
+    """The device SplitMix64 init equals the host generator bit for bit."""
+    from paper_0807_4471_amd import inputs, sclbm
+    banner("init_random vs inputs.random_densities")
+    nx, ny = 77, 45
+    a = sclbm.Simulation(nx, ny, storage="f64").init_random(12345, mean=(0.7, 0.65), amp=0.05)
+    b = sclbm.Simulation(nx, ny, storage="f64")
+    b.init_fields(inputs.random_densities(nx, ny, 12345, mean=(0.7, 0.65), amp=0.05))
+    ma, mb = a.moments(), b.moments()
+    for k in ("rhoA", "rhoB", "ux", "uy"):
+        assert np.array_equal(ma[k], mb[k]), k
+    r = inputs.random_densities(nx, ny, 12345, mean=(0.7, 0.65), amp=0.05)
+    assert np.abs(ma["rhoA"] - r[0]).max() < 1e-15
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.moments()["rhoA"], b.moments()["rhoA"])
+
+
+def test_init_with_velocity_f64():
+    rng = np.random.default_rng(3)
+    nx, ny = 31, 26
+    ux = 0.03 * rng.standard_normal((ny, nx))
+    uy = 0.03 * rng.standard_normal((ny, nx))
+    banner("f64 init with velocity field")
+    _, m = gpu_run(nx, ny, 15, ux=ux, uy=uy, storage="f64", **WORKLOAD)
+    _, _, ref = oracle_run(nx, ny, 15, ux=ux, uy=uy, **WORKLOAD)
+    e = max_err(m, ref)
+    assert e["rho"] <= 1e-12 and e["u"] <= 1e-12, e

@@ -61,8 +61,10 @@ enum { SCLBM_F64 = 0, SCLBM_F32 = 1, SCLBM_F16DEV = 2 };
 /* Lattice, couplings, relaxation times and pseudo-potential of one instance.
  * Copied at bind; the caller may free it afterwards. */
 typedef struct {
-    int32_t nx, ny;        /* lattice size: 1 <= nx, ny <= 65536 (ny >= 2 with walls),
-                              nx * ny <= 2^31 - 1                                  */
+    int32_t nx, ny;        /* lattice size: 1 <= nx, ny <= 65536 (ny >= 2 with walls);
+                              the 9 population planes of a species must span
+                              < 2 GiB (about 59M sites in FP32, 30M in FP64,
+                              119M in FP16), else SCLBM_EUNSUPPORTED           */
     int32_t boundary;      /* SCLBM_PERIODIC, or SCLBM_WALLS_Y: periodic in x,
                               half-way bounce-back walls at y = -1/2, ny - 1/2      */
     int32_t storage;       /* SCLBM_F64: FP64 populations, FP64 arithmetic;
@@ -107,10 +109,15 @@ typedef struct {
  *   tile_y >= min(4, ny) rows, one row per iteration.
  * stacked = 1 (tile, for small lattices): waves in {4, 8} stacked along y,
  *   one row each; tile_y == waves, tile_x <= 60.
+ * throttle = 1 makes each sweep iteration wait until the previous row's
+ *   stores have completed before it stages the next row (fewer memory
+ *   requests in flight, which suits DRAM-resident lattices); 0 lets stores
+ *   overlap the following rows.
  * Always tile_x >= min(32, nx).  The result of a step does not depend on
  * the tiling (bit for bit). */
 typedef struct {
     int32_t tile_x, tile_y, waves, stacked;
+    int32_t throttle, reserved;
 } sclbm_tiling;
 
 typedef struct sclbm_inst sclbm_inst;     /* opaque host handle: one lattice  */
@@ -118,6 +125,11 @@ typedef struct sclbm_batch sclbm_batch;   /* opaque host handle: a batch plan */
 
 /* Version of this ABI (SCLBM_ABI_VERSION of the build). */
 int32_t sclbm_abi_version(void);
+
+/* Host-only self-check of the lattice index helpers the kernels use (row
+ * folding for periodic and wall boundaries): 0 if consistent.  No device
+ * work; usable without a GPU. */
+int32_t sclbm_selftest(void);
 
 /* Static description of a status code.  Never NULL. */
 const char* sclbm_strerror(int32_t status);
@@ -204,21 +216,33 @@ int32_t sclbm_release(sclbm_inst* inst);
 /* ---------------- batching: many instances, one persistent launch -------- */
 
 /* Device bytes the plan of `n` instances with the given tilings needs
- * (tile table, per-instance parameters, step barrier counters), 0 if invalid. */
+ * (per-instance parameter table, tile table, grid-barrier state), 0 if the
+ * arguments are invalid (reason in sclbm_last_error). */
 size_t sclbm_batch_bytes(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling);
 
-/* Build a batch over n initialised instances (all with the same storage and
- * diag_every == 0) using the caller's device workspace (>= sclbm_batch_bytes).
- * tiling[k] applies to insts[k]; all tilings must share `waves`.  Async
- * upload on hip_stream. */
+/* Build a batch over n >= 1 initialised instances, all with the same
+ * storage and diag_every == 0, any sizes and boundaries.  tiling[k] applies
+ * to insts[k] and must have waves == 4: a sweep strip (stacked = 0,
+ * tile_x <= 252) or a stacked tile (stacked = 1, tile_x <= 60, tile_y = 4).
+ * The tile table goes into the caller's device workspace (>=
+ * sclbm_batch_bytes, 256-byte aligned), which must stay alive, unchanged,
+ * until sclbm_batch_release.  Syncs hip_stream once (table upload).  The
+ * instance handles must outlive the batch. */
 int32_t sclbm_batch_plan(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling,
                          void* dev_workspace, size_t bytes, void* hip_stream,
                          sclbm_batch** out);
 
 /* Advance instance k of the batch by steps[k] >= 0 steps in ONE persistent
- * launch (instances that finish early drop out).  Results are bitwise equal
- * to sclbm_step on each instance alone.  Async. */
+ * cooperative launch: all workgroups are co-resident and meet at a grid
+ * barrier after each step; instances with fewer steps drop out early.  Per
+ * site the arithmetic is that of sclbm_step, so each instance's result is
+ * bitwise equal to running it alone.  Async; the instances' times advance.
+ * A failed barrier (never expected) is reported by sclbm_batch_status. */
 int32_t sclbm_batch_step(sclbm_batch* batch, const int64_t* steps, void* hip_stream);
+
+/* Syncs hip_stream; EDEVICE if a grid barrier of the last launch timed out
+ * (results of that launch are then invalid), else OK. */
+int32_t sclbm_batch_status(sclbm_batch* batch, void* hip_stream);
 
 /* Free the batch handle (not the workspace or the instances). */
 int32_t sclbm_batch_release(sclbm_batch* batch);

@@ -1,0 +1,177 @@
+"""Tile-shape autotuner for the fused step.
+
+For a lattice (nx, ny), storage and boundary it enumerates the tilings the
+library accepts -- stacked tiles (4 or 8 waves along y) and sweep strips
+(1, 2 or 4 waves wide, chunk heights from 4 rows up, with or without the
+store throttle) -- times each with HIP events on the caller's GPU, and keeps
+the fastest (median of repeats; ties broken by candidate order, so the choice
+is deterministic for a given table).  Results are cached in a JSON table per
+GPU architecture (``tuning/<arch>.json`` next to this file), which
+``tiling_for`` consults; sizes without an entry take the nearest tuned size
+of the same storage and boundary, scaled to the lattice.
+
+Batch tilings (``batch=True``) are restricted to what one persistent batch
+launch accepts: 4 waves, stacked tiles or sweep strips.
+
+    python -m paper_0807_4471_amd.autotune --sizes 512 1024 4096 --storage f32
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE_DIR = os.path.join(HERE, "tuning")
+ARCH = "gfx950"
+
+
+def table_path(arch: str = ARCH) -> str:
+    return os.path.join(TABLE_DIR, f"{arch}.json")
+
+
+def load_table(arch: str = ARCH) -> dict:
+    try:
+        with open(table_path(arch)) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_table(table: dict, arch: str = ARCH):
+    os.makedirs(TABLE_DIR, exist_ok=True)
+    tmp = table_path(arch) + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, table_path(arch))
+
+
+def key(nx, ny, storage, boundary, batch=False) -> str:
+    return f"{'batch/' if batch else ''}{storage}/{boundary}/{nx}x{ny}"
+
+
+def _strip_width(nx: int, wmax: int) -> int:
+    ns = -(-nx // wmax)
+    return max(-(-nx // ns), min(32, nx))
+
+
+def candidates(nx: int, ny: int, batch: bool = False) -> list:
+    """Tilings (tile_x, tile_y, waves, stacked, throttle) in a fixed order."""
+    out = []
+    for rw in ((4,) if batch else (4, 8)):
+        out.append((min(_strip_width(nx, 60), 60), rw, rw, 1, 0))
+    for cw in ((4,) if batch else (1, 2, 4)):
+        W = _strip_width(nx, 64 * cw - 4)
+        ns = -(-nx // W)
+        heights = [h for h in (4, 8, 16, 32, 64, 128, 256) if h < ny] + [ny]
+        # heights giving ~1, 2 and 3 resident workgroups of this width per CU
+        for per_cu in (1, 2, 3):
+            target = max(1, (256 * per_cu * 4 // cw) // ns) if not batch else 0
+            if target:
+                heights.append(max(4, -(-ny // target)))
+        for H in sorted(set(min(max(h, 4), max(ny, 4)) for h in heights)):
+            for th in (0, 1):
+                out.append((W, H, cw, 0, th))
+    seen, uniq = set(), []
+    for c in out:
+        if c not in seen:
+            seen.add(c)
+            uniq.append(c)
+    return uniq
+
+
+def measure(sim, tiling, steps: int, repeats: int = 3) -> float:
+    """Median microseconds per step of `sim` with `tiling`."""
+    import torch
+    sim.set_tiling(*tiling)
+    sim.step(max(2, steps // 10))
+    times = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e3 / steps)
+    return statistics.median(times)
+
+
+def tune(nx: int, ny: int, storage: str = "f32", boundary: str = "periodic", batch=False,
+         steps: int | None = None, table: dict | None = None, verbose=False, **phys) -> tuple:
+    """Time every candidate and record the fastest in `table` (or the file)."""
+    from . import sclbm
+    own_table = table is None
+    if own_table:
+        table = load_table()
+    sim = sclbm.Simulation(nx, ny, storage=storage, boundary=boundary,
+                           wall_u=(0.0, 0.05) if boundary == "walls" else (0.0, 0.0), **phys)
+    sim.init_random(1)
+    if steps is None:  # about 20 ms of work per measurement at ~30 GLUPS
+        steps = int(min(2000, max(10, 6e8 / (nx * ny))))
+    results = []
+    for c in candidates(nx, ny, batch):
+        us = measure(sim, c, steps)
+        results.append((us, c))
+        if verbose:
+            print(f"  {key(nx, ny, storage, boundary, batch)} {c}: {us:9.2f} us/step", flush=True)
+    best_us, best = min(results, key=lambda r: r[0])
+    table[key(nx, ny, storage, boundary, batch)] = {
+        "tiling": list(best), "us_per_step": round(best_us, 3),
+        "mlups": round(nx * ny / best_us, 1), "candidates": len(results)}
+    if own_table:
+        save_table(table)
+    sim.close()
+    return best
+
+
+def tiling_for(nx: int, ny: int, storage: str = "f32", boundary: str = "periodic",
+               batch: bool = False, table: dict | None = None):
+    """Tuned tiling for this lattice, or one derived from the nearest tuned
+    size (strip width recomputed, chunk height scaled); None if the table has
+    nothing for this storage/boundary."""
+    table = load_table() if table is None else table
+    k = key(nx, ny, storage, boundary, batch)
+    if k in table:
+        return tuple(table[k]["tiling"])
+    prefix = f"{'batch/' if batch else ''}{storage}/{boundary}/"
+    best = None
+    for kk, v in table.items():
+        if not kk.startswith(prefix):
+            continue
+        tx, ty = (int(a) for a in kk[len(prefix):].split("x"))
+        d = abs((tx * ty) ** 0.5 - (nx * ny) ** 0.5)
+        if best is None or d < best[0]:
+            best = (d, tx, ty, v["tiling"])
+    if best is None:
+        return None
+    _, tx, ty, (W, H, waves, stacked, throttle) = best
+    if stacked:
+        return (min(_strip_width(nx, 60), 60), H, waves, 1, throttle)
+    Wn = _strip_width(nx, 64 * waves - 4)
+    Hn = max(4, min(ny, round(H * ny / ty)))
+    return (Wn, Hn, waves, 0, throttle)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 256, 512, 1024, 2048, 4096])
+    ap.add_argument("--storage", nargs="+", default=["f32", "f16dev", "f64"])
+    ap.add_argument("--boundary", nargs="+", default=["periodic"])
+    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    a = ap.parse_args()
+    table = load_table()
+    for st in a.storage:
+        for bc in a.boundary:
+            for n in a.sizes:
+                best = tune(n, n, st, bc, batch=a.batch, table=table, verbose=a.verbose)
+                e = table[key(n, n, st, bc, a.batch)]
+                print(f"{key(n, n, st, bc, a.batch)}: {best}  {e['us_per_step']} us/step  "
+                      f"{e['mlups']} MLUPS", flush=True)
+                save_table(table)
+
+
+if __name__ == "__main__":
+    main()

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsclbm.so")
-SOURCES = ["sclbm_kernels.hip", "sclbm_api.cpp", "sclbm_batch.cpp"]
+SOURCES = ["sclbm_kernels.hip", "sclbm_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "sclbm.h"
 #include "sclbm_internal.h"
@@ -77,6 +78,15 @@ int32_t validate(const sclbm_desc* d)
     if (!isfinite(d->body_F0)) return fail(SCLBM_EINVAL, "body_F0 must be finite");
     if (d->diag_every < 0) return fail(SCLBM_EINVAL, "diag_every must be >= 0");
     if (d->reserved != 0) return fail(SCLBM_EINVAL, "reserved must be 0");
+    // populations are addressed through one buffer resource per species
+    // with 32-bit offsets: its 9 planes must span < 2^31 bytes
+    const int64_t rows = d->ny + (d->boundary == SCLBM_WALLS_Y ? 2 : 0);
+    const int64_t plane_bytes = ((((int64_t)d->nx + 63) / 64 * 64) * rows + 128) *
+                                (int64_t)(d->storage == SCLBM_F64 ? 8 : d->storage == SCLBM_F32 ? 4 : 2);
+    if (9 * plane_bytes >= (int64_t)1 << 31)
+        return fail(SCLBM_EUNSUPPORTED,
+                    "the 9 population planes of a species would span %lld bytes (>= 2 GiB); "
+                    "split the lattice", (long long)(9 * plane_bytes));
     return SCLBM_OK;
 }
 
@@ -179,13 +189,15 @@ struct sclbm_inst {
     int64_t wall_steps;
     int cw, W, H, nstrips, nchunks;
     int stacked;          // 1: tile mode, cw waves stacked along y (H == cw)
+    int throttle;         // sweep iterations wait for the previous row's stores
 };
 
 namespace {
 
-void set_tiling(sclbm_inst* h, int cw, int W, int H, int stacked = 0)
+void set_tiling(sclbm_inst* h, int cw, int W, int H, int stacked = 0, int throttle = 0)
 {
     h->stacked = stacked;
+    h->throttle = throttle;
     h->cw = cw;
     h->W = W;
     h->H = H;
@@ -215,25 +227,14 @@ void default_tiling(sclbm_inst* h)
     const int target_blocks = std::max(1, 2048 / cw);
     int nc = std::max(1, target_blocks / ns);
     int H = std::max(MIN_TILE_Y, (ny + nc - 1) / nc);
-    set_tiling(h, cw, W, H);
-}
-
-// Seed of the FP16 stochastic rounding in the step that starts at time t: a
-// fixed function of t, so results are reproducible and independent of how
-// the steps are launched.
-uint32_t step_seed(int64_t t)
-{
-    uint64_t z = (uint64_t)t * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return (uint32_t)(z ^ (z >> 31));
+    set_tiling(h, cw, W, H, 0, 1);
 }
 
 template <class S, class A>
 Inst<S, A> make_inst(const sclbm_inst* h, const Coef<A>& c, int from, int to, int W, int H)
 {
     Inst<S, A> I{};
-    I.seed = step_seed(h->t);
+    I.t = h->t;
     I.fin = reinterpret_cast<const S*>(h->buf + h->L.off_f[from]);
     I.fout = reinterpret_cast<S*>(h->buf + h->L.off_f[to]);
     I.g = h->L.g;
@@ -242,6 +243,7 @@ Inst<S, A> make_inst(const sclbm_inst* h, const Coef<A>& c, int from, int to, in
     I.H = H;
     I.nstrips = (h->d.nx + W - 1) / W;
     I.nchunks = (h->d.ny + H - 1) / H;
+    I.throttle = h->throttle;
     I.partials = reinterpret_cast<double*>(h->buf + h->L.off_partials);
     I.wall_acc = reinterpret_cast<double*>(h->buf + h->L.off_wall);
     return I;
@@ -314,6 +316,28 @@ int32_t read_wall(const sclbm_inst* h, double* host, hipStream_t st)
 extern "C" {
 
 int32_t sclbm_abi_version(void) { return SCLBM_ABI_VERSION; }
+
+// Host self-check of index helpers shared with the kernels (no device work):
+// every row a kernel may stage, r in [-2, ny + 9], must fold into [0, ny),
+// and the folds must be the periodic wrap / the mirror images.  Returns 0 on
+// success, else the first failing ny.
+int32_t sclbm_selftest(void)
+{
+    for (int ny = 1; ny <= 40; ++ny)
+        for (int walls = 0; walls < 2; ++walls) {
+            if (walls && ny < 2) continue;
+            for (int r = -2; r <= ny + 9; ++r) {
+                const int f = fold_row(r, ny, walls != 0);
+                if (f < 0 || f >= ny) return ny;
+                if (!walls && f != ((r % ny) + ny) % ny) return ny;
+                if (walls && r >= -ny && r < 2 * ny) {
+                    const int m = r < 0 ? -1 - r : (r >= ny ? 2 * ny - 1 - r : r);
+                    if (f != m) return ny;
+                }
+            }
+        }
+    return 0;
+}
 
 const char* sclbm_strerror(int32_t status)
 {
@@ -449,6 +473,8 @@ int32_t sclbm_set_tiling(sclbm_inst* h, const sclbm_tiling* tl)
     if (!h || !tl) return fail(SCLBM_EINVAL, "NULL argument");
     const int cw = tl->waves, W = tl->tile_x, H = tl->tile_y;
     if (tl->stacked != 0 && tl->stacked != 1) return fail(SCLBM_EINVAL, "stacked must be 0 or 1");
+    if (tl->throttle != 0 && tl->throttle != 1) return fail(SCLBM_EINVAL, "throttle must be 0 or 1");
+    if (tl->reserved != 0) return fail(SCLBM_EINVAL, "reserved must be 0");
     if (tl->stacked) {
         if (cw != 4 && cw != 8) return fail(SCLBM_EINVAL, "stacked tiles need waves 4 or 8");
         if (H != cw) return fail(SCLBM_EINVAL, "stacked tiles need tile_y == waves");
@@ -459,7 +485,7 @@ int32_t sclbm_set_tiling(sclbm_inst* h, const sclbm_tiling* tl)
         if (H < std::min(MIN_TILE_Y, h->d.ny)) return fail(SCLBM_EINVAL, "tile_y %d too small", H);
     }
     if (W < std::min(MIN_TILE_X, h->d.nx)) return fail(SCLBM_EINVAL, "tile_x %d too small", W);
-    set_tiling(h, cw, W, H, tl->stacked);
+    set_tiling(h, cw, W, H, tl->stacked, tl->throttle);
     return SCLBM_OK;
 }
 
@@ -470,6 +496,8 @@ int32_t sclbm_get_tiling(const sclbm_inst* h, sclbm_tiling* out)
     out->tile_y = h->H;
     out->waves = h->cw;
     out->stacked = h->stacked;
+    out->throttle = h->throttle;
+    out->reserved = 0;
     return SCLBM_OK;
 }
 
@@ -608,6 +636,217 @@ int32_t sclbm_restore(sclbm_inst* h, const void* host_buf, size_t bytes, void* s
     h->t = hd.t;
     h->inited = true;
     h->fused_step = -1;
+    return SCLBM_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batching
+
+struct sclbm_batch {
+    int n = 0, storage = 0, nitems = 0, grid = 0;
+    std::vector<sclbm_inst*> insts;
+    std::vector<sclbm_tiling> tl;
+    char* ws = nullptr;
+    size_t inst_bytes = 0, off_items = 0, off_ctl = 0, total = 0;
+    std::vector<char> host_insts;  // staging of the per-launch instance table
+    hipEvent_t uploaded = nullptr;  // the staging buffer may be reused after it
+};
+
+namespace {
+
+size_t batch_inst_size(int storage)
+{
+    switch (storage) {
+    case SCLBM_F64: return sizeof(BatchInst<double, double>);
+    case SCLBM_F32: return sizeof(BatchInst<float, float>);
+    default: return sizeof(BatchInst<_Float16, float>);
+    }
+}
+
+int32_t check_batch_tiling(const sclbm_inst* h, const sclbm_tiling& t)
+{
+    if ((t.throttle != 0 && t.throttle != 1) || t.reserved != 0)
+        return fail(SCLBM_EINVAL, "throttle must be 0 or 1, reserved 0");
+    if (t.waves != 4) return fail(SCLBM_EINVAL, "batch tilings need waves == 4");
+    if (t.stacked) {
+        if (t.tile_y != 4 || t.tile_x > 60)
+            return fail(SCLBM_EINVAL, "stacked batch tiles are tile_x <= 60 by 4 rows");
+    } else {
+        if (t.tile_x > 252) return fail(SCLBM_EINVAL, "batch strips are at most 252 wide");
+        if (t.tile_y < std::min(MIN_TILE_Y, h->d.ny)) return fail(SCLBM_EINVAL, "tile_y too small");
+    }
+    if (t.tile_x < std::min(MIN_TILE_X, h->d.nx)) return fail(SCLBM_EINVAL, "tile_x too small");
+    return SCLBM_OK;
+}
+
+int32_t batch_layout(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tl,
+                     size_t* inst_bytes, size_t* off_items, size_t* off_ctl, size_t* total,
+                     int* nitems)
+{
+    if (!insts || !tl || n < 1) return fail(SCLBM_EINVAL, "empty batch or NULL arrays");
+    const int storage = insts[0] ? insts[0]->d.storage : -1;
+    int64_t items = 0;
+    for (int k = 0; k < n; ++k) {
+        const sclbm_inst* h = insts[k];
+        if (!h) return fail(SCLBM_EINVAL, "instance %d is NULL", k);
+        if (h->d.storage != storage) return fail(SCLBM_EINVAL, "mixed storage types in a batch");
+        if (h->d.diag_every != 0) return fail(SCLBM_EUNSUPPORTED, "fused diagnostics in a batch");
+        int32_t rc = check_batch_tiling(h, tl[k]);
+        if (rc) return rc;
+        items += (int64_t)((h->d.nx + tl[k].tile_x - 1) / tl[k].tile_x) *
+                 ((h->d.ny + tl[k].tile_y - 1) / tl[k].tile_y);
+    }
+    if (items > (1 << 30)) return fail(SCLBM_ESIZE, "too many tiles");
+    *inst_bytes = align_up(batch_inst_size(storage) * n, ALIGN);
+    *off_items = *inst_bytes;
+    *off_ctl = *off_items + align_up(sizeof(BatchItem) * (size_t)items, ALIGN);
+    *total = *off_ctl + align_up(sizeof(BatchCtl), ALIGN);
+    *nitems = (int)items;
+    return SCLBM_OK;
+}
+
+template <class S, class A>
+void fill_batch_inst(const sclbm_inst* h, const Coef<A>& c, const sclbm_tiling& t, int64_t steps,
+                     void* dst)
+{
+    BatchInst<S, A> b{};
+    b.I = make_inst<S, A>(h, c, h->cur, 1 - h->cur, t.tile_x, t.tile_y);
+    b.I.throttle = t.throttle;
+    b.steps = steps;
+    b.stacked = t.stacked;
+    memcpy(dst, &b, sizeof b);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sclbm_batch_bytes(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling)
+{
+    size_t ib, oi, oc, total;
+    int ni;
+    if (batch_layout(insts, n, tiling, &ib, &oi, &oc, &total, &ni)) return 0;
+    return total;
+}
+
+int32_t sclbm_batch_plan(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling,
+                         void* dev_workspace, size_t bytes, void* stream, sclbm_batch** out)
+{
+    if (!out) return fail(SCLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t ib, oi, oc, total;
+    int ni;
+    int32_t rc = batch_layout(insts, n, tiling, &ib, &oi, &oc, &total, &ni);
+    if (rc) return rc;
+    for (int k = 0; k < n; ++k)
+        if (!insts[k]->inited) return fail(SCLBM_ESTATE, "instance %d not initialised", k);
+    if (!dev_workspace || (uintptr_t)dev_workspace % ALIGN)
+        return fail(SCLBM_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (bytes < total) return fail(SCLBM_ESIZE, "workspace of %zu bytes < %zu needed", bytes, total);
+    const int storage = insts[0]->d.storage;
+    const int grid = batch_grid(storage);
+    if (grid <= 0) return fail(SCLBM_EDEVICE, "cannot size the cooperative grid");
+    sclbm_batch* b = new (std::nothrow) sclbm_batch();
+    if (!b) return fail(SCLBM_EINVAL, "out of host memory");
+    b->n = n;
+    b->storage = storage;
+    b->nitems = ni;
+    b->grid = std::min(grid, ni);
+    b->insts.assign(insts, insts + n);
+    b->tl.assign(tiling, tiling + n);
+    b->ws = static_cast<char*>(dev_workspace);
+    b->inst_bytes = ib;
+    b->off_items = oi;
+    b->off_ctl = oc;
+    b->total = total;
+    b->host_insts.resize(ib);
+    // tile table: instance-major, each instance's tiles strip-major
+    std::vector<BatchItem> items;
+    items.reserve(ni);
+    for (int k = 0; k < n; ++k) {
+        const sclbm_inst* h = insts[k];
+        const int ns = (h->d.nx + tiling[k].tile_x - 1) / tiling[k].tile_x;
+        const int nc = (h->d.ny + tiling[k].tile_y - 1) / tiling[k].tile_y;
+        for (int tt = 0; tt < ns * nc; ++tt) items.push_back(BatchItem{k, tt});
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->ws + oi, items.data(), sizeof(BatchItem) * items.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // `items` is a local
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch plan upload");
+    }
+    *out = b;
+    return SCLBM_OK;
+}
+
+int32_t sclbm_batch_step(sclbm_batch* b, const int64_t* steps, void* stream)
+{
+    if (!b || !steps) return fail(SCLBM_EINVAL, "NULL argument");
+    int64_t max_steps = 0;
+    for (int k = 0; k < b->n; ++k) {
+        if (steps[k] < 0) return fail(SCLBM_EINVAL, "steps[%d] < 0", k);
+        if (!b->insts[k]->inited) return fail(SCLBM_ESTATE, "instance %d not initialised", k);
+        max_steps = std::max(max_steps, steps[k]);
+    }
+    if (max_steps == 0) return SCLBM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // the staging buffer of the previous launch must have been consumed
+    hipError_t e = hipEventSynchronize(b->uploaded);
+    if (e != hipSuccess) return hip_fail(e, "batch staging wait");
+    const size_t isz = batch_inst_size(b->storage);
+    for (int k = 0; k < b->n; ++k) {
+        const sclbm_inst* h = b->insts[k];
+        void* dst = b->host_insts.data() + isz * k;
+        if (b->storage == SCLBM_F64)
+            fill_batch_inst<double, double>(h, h->cd, b->tl[k], steps[k], dst);
+        else if (b->storage == SCLBM_F32)
+            fill_batch_inst<float, float>(h, h->cf, b->tl[k], steps[k], dst);
+        else
+            fill_batch_inst<_Float16, float>(h, h->cf, b->tl[k], steps[k], dst);
+    }
+    e = hipMemcpyAsync(b->ws, b->host_insts.data(), isz * b->n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(b->uploaded, st);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws + b->off_ctl, 0, sizeof(BatchCtl), st);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    e = launch_batch(b->storage, b->ws, reinterpret_cast<const BatchItem*>(b->ws + b->off_items),
+                     b->nitems, max_steps, reinterpret_cast<BatchCtl*>(b->ws + b->off_ctl),
+                     b->grid, st);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    for (int k = 0; k < b->n; ++k) {
+        sclbm_inst* h = b->insts[k];
+        h->t += steps[k];
+        h->cur ^= (int)(steps[k] & 1);
+        if (h->d.boundary == SCLBM_WALLS_Y) h->wall_steps += steps[k];
+    }
+    return SCLBM_OK;
+}
+
+int32_t sclbm_batch_status(sclbm_batch* b, void* stream)
+{
+    if (!b) return fail(SCLBM_EINVAL, "NULL batch");
+    BatchCtl c;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(&c, b->ws + b->off_ctl, sizeof c, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "batch status");
+    if (c.err) return fail(SCLBM_EDEVICE, "batch grid barrier timed out; results invalid");
+    return SCLBM_OK;
+}
+
+int32_t sclbm_batch_release(sclbm_batch* b)
+{
+    if (b) {
+        if (b->uploaded) {
+            (void)hipEventSynchronize(b->uploaded);
+            (void)hipEventDestroy(b->uploaded);
+        }
+        delete b;
+    }
     return SCLBM_OK;
 }
 

@@ -27,7 +27,9 @@ enum { M_STEP = 0, M_STEP_DIAG = 1, M_READ = 2, M_DIAG = 3 };
 // Population storage in HBM: f[s][i][row][x], s-major then direction, rows of
 // `pitch` elements, `plane` elements between consecutive (s, i) planes.  With
 // walls there are two ghost rows (row 0 below the channel, row ny + 1 above);
-// real row y sits at row y + walls.  What is stored is the post-collision
+// real row y sits at row y + walls.  The 9 planes of a species span < 2^31
+// bytes (they are addressed through one buffer resource with 32-bit
+// offsets).  What is stored is the post-collision
 // set f*(t-1); a step pulls f_i(x, t) = f*_i(x - c_i, t-1).
 struct Geo {
     int32_t nx, ny, walls, rows, pitch;
@@ -63,17 +65,59 @@ struct Inst {
     Coef<A> c;
     int32_t W, H;               // interior columns per strip, rows per chunk
     int32_t nstrips, nchunks;
-    uint32_t seed;              // per-step key of the FP16 stochastic rounding
-    uint32_t pad_;
+    int32_t throttle;           // wait for the previous row's stores each iteration
+    int32_t pad2_;
+    int64_t t;                  // time at the start of this step (FP16 rounding key)
     double* partials;           // [nblocks][NDIAG] (diagnostic modes)
     double* wall_acc;           // [2 walls][2 comps][nx], accumulated every step
     double* out[5];             // READ mode: rhoA, rhoB, ux, uy, sxy (any NULL)
 };
 
+// One instance inside a persistent batch launch.  `I` describes the
+// instance's first step of the launch (fin/fout, time); later steps swap the
+// population copies and advance the time.
+template <class S, class A>
+struct BatchInst {
+    Inst<S, A> I;
+    int64_t steps;    // steps of this instance in this launch
+    int32_t stacked;  // 1: stacked 4-wave tiles, 0: 4-wave-wide sweep strips
+    int32_t pad_;
+};
+
+struct BatchItem {
+    int32_t inst, tile;  // tile = strip * nchunks + chunk of that instance
+};
+
+// Grid-barrier state of a batch launch (zeroed before each launch).
+struct BatchCtl {
+    uint32_t count, gen, err, pad_;
+};
+
+// Row of the lattice whose values a (ring) row index r stands for.
+// Periodic: r mod ny.  Walls: the mirror images about the wall planes
+// y = -1/2 and y = ny - 1/2 repeat with period 2 ny (even extension), so any
+// r (tile rows may reach y0 + RW + 1 >= 2 ny on very short lattices) folds
+// into [0, ny).
+__host__ __device__ inline int fold_row(int r, int ny, bool walls)
+{
+    if (!walls) {
+        r %= ny;
+        return r < 0 ? r + ny : r;
+    }
+    const int p = 2 * ny;
+    r %= p;
+    if (r < 0) r += p;
+    return r < ny ? r : p - 1 - r;
+}
+
 // Host-side launchers (defined in sclbm_kernels.hip).
 hipError_t launch_sweep(int storage, int cw, int mode, const void* inst, int nblocks,
                         hipStream_t st);
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
+// Largest co-resident grid of the batch kernel for this storage (0 on error).
+int batch_grid(int storage);
+hipError_t launch_batch(int storage, const void* insts, const BatchItem* items, int nitems,
+                        int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st);
 hipError_t launch_init(int storage, const void* inst, const double* rhoA, const double* rhoB,
                        const double* ux, const double* uy, int random, uint64_t seed,
                        double meanA, double meanB, double amp, hipStream_t st);

@@ -54,6 +54,17 @@ constexpr int CX_[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int CY_[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int OPP_[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
+// Key of the FP16 stochastic rounding in the step that starts at time t: a
+// fixed function of t (SplitMix64 output function), so results are
+// reproducible and independent of how steps are launched or batched.
+__device__ __forceinline__ uint32_t step_seed(int64_t t)
+{
+    uint64_t z = (uint64_t)t * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)(z ^ (z >> 31));
+}
+
 // 32-bit integer finaliser "lowbias32" (C. Wellons, hash-prospector): the
 // random bits of the stochastic rounding, keyed by step seed, site, species.
 __device__ __forceinline__ uint32_t hash32(uint32_t x)
@@ -64,6 +75,43 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x)
     x *= 0x846ca68bu;
     x ^= x >> 16;
     return x;
+}
+
+// Populations are loaded and stored through one raw buffer resource per
+// species (its 9 planes, < 2^31 bytes) with a 32-bit per-lane byte offset:
+// column (per lane) + row and plane (uniform).  A lane that owns no site
+// stores with offset DROP + uniform part >= 2^31, outside the resource, and
+// the hardware range check discards the write; so every lane executes the
+// store instruction (no divergent branch) and nothing is written for it.
+constexpr uint32_t DROP = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t species_rsrc(const char* base, int nrec)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, nrec, 0x00020000);
+}
+
+template <class S>
+__device__ __forceinline__ S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff)
+{
+    if constexpr (sizeof(S) == 8)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+    else if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+    else
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0));
+}
+
+template <class S>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, S v)
+{
+    if constexpr (sizeof(S) == 8) {
+        typedef unsigned u2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
+    } else if constexpr (sizeof(S) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, 0, 0);
+    }
 }
 
 template <class T>
@@ -112,6 +160,9 @@ struct Sweep {
     const char* finb;
     char* foutb;
     int64_t plane_b, pitch_b;
+    __amdgpu_buffer_rsrc_t rin[2], rout[2];  // per-species resources
+    uint32_t sw_, sm_, sp_;                  // store column offsets, DROP if not own
+    uint32_t seed;  // FP16 stochastic-rounding key of this step
     S R[18];  // raw loads of the next row
 
     __device__ Sweep(const Inst<S, A>& I_, int strip, A2 (*lp)[NC], A2 (*lr)[NC], double* acc_)
@@ -133,21 +184,19 @@ struct Sweep {
         foutb = reinterpret_cast<char*>(I.fout);
         plane_b = I.g.plane * (int64_t)sizeof(S);
         pitch_b = (int64_t)I.g.pitch * (int64_t)sizeof(S);
+        const int nrec = (int)(9 * plane_b);
+        rin[0] = species_rsrc(finb, nrec);
+        rin[1] = species_rsrc(finb + 9 * plane_b, nrec);
+        rout[0] = species_rsrc(foutb, nrec);
+        rout[1] = species_rsrc(foutb + 9 * plane_b, nrec);
+        sw_ = own ? cw : DROP;
+        sm_ = own ? cm : DROP;
+        sp_ = own ? cp : DROP;
+        seed = DEV ? step_seed(I.t) : 0u;
     }
 
-    // Ring row r (may lie outside the lattice) -> real row: periodic wrap, or
-    // the mirror image about the wall planes y = -1/2, ny - 1/2.
-    __device__ int real_row(int r) const
-    {
-        if constexpr (WALLS) {
-            if (r < 0) r = -1 - r;
-            if (r > ny - 1) r = 2 * ny - 1 - r;
-            return r;
-        } else {
-            r %= ny;
-            return r < 0 ? r + ny : r;
-        }
-    }
+    // Ring row r (may lie outside the lattice) -> real row in [0, ny).
+    __device__ int real_row(int r) const { return fold_row(r, ny, WALLS); }
 
     // Issue the 18 loads f_i(x, t) = f*_i(x - c_i, t-1) of ring row r into R.
     // Plane and row parts of each address are uniform; each lane adds one of
@@ -167,16 +216,15 @@ struct Sweep {
             rm = rr == 0 ? ny - 1 : rr - 1;
             rp = rr == ny - 1 ? 0 : rr + 1;
         }
-        const char* b0 = finb + (int64_t)r0 * pitch_b;
-        const char* bm = finb + (int64_t)rm * pitch_b;
-        const char* bp = finb + (int64_t)rp * pitch_b;
+        const uint32_t o0 = (uint32_t)(r0 * pitch_b), om = (uint32_t)(rm * pitch_b),
+                       op = (uint32_t)(rp * pitch_b);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const char* rb = CY_[i] > 0 ? bm : CY_[i] < 0 ? bp : b0;
+                const uint32_t ro = CY_[i] > 0 ? om : CY_[i] < 0 ? op : o0;
                 const uint32_t co = CX_[i] > 0 ? cm : CX_[i] < 0 ? cp : cw;
-                R[s * 9 + i] = *(const S*)(rb + (int64_t)(s * 9 + i) * plane_b + co);
+                R[s * 9 + i] = bload<S>(rin[s], co + (ro + (uint32_t)(i * plane_b)));
             }
     }
 
@@ -249,15 +297,21 @@ struct Sweep {
     }
 
     // Finish row y: forces from the LDS ring (slot sb holds row y-2), then
-    // collision + store (step), moment read-out or diagnostics.
+    // collision + store (step), moment read-out or diagnostics.  Every lane
+    // runs it: lanes owning no site (halo lanes, columns beyond nx) read a
+    // clamped LDS column and their stores are dropped by the buffer range
+    // check, so the stores are not under a divergent branch and the
+    // compiler's wait counts stay exact (otherwise the next row's loads
+    // would also wait for these stores).
     __device__ void finish(int y, int sb, A* v)
     {
         const Coef<A>& c = I.c;
+        const int tc = own ? t : 2;
         int sl[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) sl[k] = sb + k >= NS ? sb + k - NS : sb + k;
-        auto Ps = [&](int dx, int dy) { return lpsi[sl[dy + 2]][t + dx]; };
-        auto Rs = [&](int dx, int dy) { return lrho[sl[dy + 2]][t + dx]; };
+        auto Ps = [&](int dx, int dy) { return lpsi[sl[dy + 2]][tc + dx]; };
+        auto Rs = [&](int dx, int dy) { return lrho[sl[dy + 2]][tc + dx]; };
         auto dif = [](A2 a, A2 b) { return A2{a.x - b.x, a.y - b.y}; };
         // Psi differences over the 12 opposite pairs (both species)
         const A2 a10 = dif(Ps(1, 0), Ps(-1, 0)), a01 = dif(Ps(0, 1), Ps(0, -1));
@@ -321,12 +375,13 @@ struct Sweep {
             }
             if constexpr (MODE == M_READ) {
                 const int64_t n = (int64_t)y * nx + xw;
+                if (!own) return;
                 if (I.out[0]) I.out[0][n] = (double)rho[0];
                 if (I.out[1]) I.out[1][n] = (double)rho[1];
                 if (I.out[2]) I.out[2][n] = (double)vx;
                 if (I.out[3]) I.out[3][n] = (double)vy;
                 if (I.out[4]) I.out[4][n] = (double)sxy;
-            } else {
+            } else if (own) {
                 acc[D_MASS_A] += (double)rhod[0] + (double)c.rho_base[0] * DEV;
                 acc[D_MASS_B] += (double)rhod[1] + (double)c.rho_base[1] * DEV;
                 acc[D_MOM_X] += (double)mx;
@@ -347,15 +402,15 @@ struct Sweep {
             const A iden = den > A(0) ? rcp<T>(den) : A(0);
             const A upx = nmx * iden, upy = nmy * iden;
             const int ro = y + (WALLS ? 1 : 0);
-            char* const rowb = foutb + (int64_t)ro * pitch_b;  // uniform
+            const uint32_t soff = (uint32_t)(ro * pitch_b);  // uniform row offsets
             // Wall rows: a population that would leave the channel returns to
             // its node reversed, minus 2 w_i rho (c_i.u_w)/c_s^2 (half-way
             // bounce-back), written to the ghost row where the next pull of
             // the reversed direction looks for it.  The outgoing value itself
             // is never read and is not stored.
-            const bool bot = WALLS && y == 0, top = WALLS && y == ny - 1;
+            const bool bot = WALLS && y == 0, top = WALLS && y == ny - 1;  // uniform
             const A u6 = WALLS ? c.wall6u[top ? 1 : 0] : A(0);
-            char* const ghostb = foutb + (int64_t)(top ? ny + 1 : 0) * pitch_b;  // uniform
+            const uint32_t goff = (uint32_t)((top ? ny + 1 : 0) * pitch_b);
             double mxw = 0.0, myw = 0.0;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -367,28 +422,30 @@ struct Sweep {
                 [[maybe_unused]] A qsum = A(0);
 #pragma unroll
                 for (int i = 1; i < 9; ++i) {
-                    const bool out = (bot && CY_[i] < 0) || (top && CY_[i] > 0);
+                    const bool out = (bot && CY_[i] < 0) || (top && CY_[i] > 0);  // uniform
                     A val = f[i];
-                    S* dst = (S*)(rowb + (int64_t)(s * 9 + i) * plane_b + cw);
+                    int k = s * 9 + i;
+                    uint32_t col = sw_, ro_off = soff;
                     if (out) {
                         val = f[i] - A(CX_[i]) * corr;
-                        const uint32_t col = CX_[i] > 0 ? cp : CX_[i] < 0 ? cm : cw;
-                        dst = (S*)(ghostb + (int64_t)(s * 9 + OPP_[i]) * plane_b + col);
+                        k = s * 9 + OPP_[i];
+                        col = CX_[i] > 0 ? sp_ : CX_[i] < 0 ? sm_ : sw_;
+                        ro_off = goff;
                         mxw += (double)CX_[i] * ((double)f[i] + (double)val);
                         myw += (double)CY_[i] * ((double)f[i] + (double)val);
                         if constexpr (DEV)  // the reference populations' share
                             myw += (double)CY_[i] * 2.0 * (double)c.rho_base[s] *
                                    (CX_[i] == 0 ? W1 : W2);
                     }
+                    const uint32_t dst = col + (ro_off + (uint32_t)((k - 9 * s) * plane_b));
                     if constexpr (DEV) {
                         const _Float16 h = (_Float16)val;
-                        *dst = h;
+                        bstore<_Float16>(rout[s], dst, h);
                         qsum += (float)h;  // exact: sum of binary16 values
                     } else {
-                        *dst = (S)val;
+                        bstore<S>(rout[s], dst, (S)val);
                     }
                 }
-                S* d0 = (S*)(rowb + (int64_t)(s * 9) * plane_b + cw);
                 if constexpr (DEV) {
                     // The rest population absorbs the rounding of the other
                     // eight deviations and is itself rounded stochastically
@@ -396,17 +453,17 @@ struct Sweep {
                     // zero-mean rounding.
                     const float h0 = rhod[s] - qsum;
                     const uint32_t r = hash32(
-                        I.seed ^ (uint32_t)(((uint32_t)y * (uint32_t)nx + (uint32_t)xw) * 2u + s));
+                        seed ^ (uint32_t)(((uint32_t)y * (uint32_t)nx + (uint32_t)xw) * 2u + s));
                     typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
                     h2_t hv = {(_Float16)0, (_Float16)0};
                     hv = __builtin_amdgcn_cvt_sr_f16_f32(hv, h0, r, false);
-                    *d0 = hv[0];
+                    bstore<_Float16>(rout[s], sw_ + soff, hv[0]);
                 } else {
-                    *d0 = (S)f[0];
+                    bstore<S>(rout[s], sw_ + soff, (S)f[0]);
                 }
             }
             if constexpr (WALLS) {
-                if (bot || top) {
+                if ((bot || top) && own) {
                     double* wa = I.wall_acc + (top ? 2 : 0) * (int64_t)nx;
                     wa[xw] += mxw;
                     wa[nx + xw] += myw;
@@ -422,6 +479,10 @@ struct Sweep {
     {
         const int snew = sb + 4 >= 6 ? sb - 2 : sb + 4;
         if constexpr (!PF) load_into(y + 2, PC);
+        // optional throttle: all earlier memory operations (the previous
+        // row's stores included) complete before this row is staged
+        // (s_waitcnt vmcnt(0); expcnt, lgkmcnt untouched)
+        if (I.throttle) __builtin_amdgcn_s_waitcnt(0x0F70);
         if constexpr (DEV) convert(PC);
         stage(snew, PC);
         __syncthreads();
@@ -433,7 +494,7 @@ struct Sweep {
                     load_into(y + 3, PD);
             }
         }
-        if (own) finish(y, sb, PA);
+        finish(y, sb, PA);
         sb = sb == 5 ? 0 : sb + 1;
     }
 
@@ -535,16 +596,12 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
 // y0-2, y0-1, y0+RW, y0+RW+1; one barrier; every wave finishes its row.  The
 // dependency chain per workgroup is one row instead of H+4 rows.
 template <class T, int RW, bool WALLS, int MODE>
-__global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typename T::A> I)
+__device__ __forceinline__ void tile_body(const Inst<typename T::S, typename T::A>& I, int strip,
+                                          int chunk, typename T::A2 (*lpsi)[64],
+                                          typename T::A2 (*lrho)[64], double* acc)
 {
     static_assert(RW >= 4, "four waves stage the halo rows");
     using A = typename T::A;
-    __shared__ typename T::A2 lpsi[RW + 4][64];
-    __shared__ typename T::A2 lrho[RW + 4][64];
-    __shared__ double red[RW][NDIAG];
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     Sweep<T, 1, WALLS, MODE, RW + 4> sw(I, strip, lpsi, lrho, acc);
     const int w = threadIdx.x >> 6;  // uniform per wave
     const int y0 = chunk * RW;
@@ -561,7 +618,19 @@ __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typen
     }
     sw.stage(w + 2, P);
     __syncthreads();
-    if (sw.own && y0 + w < sw.ny) sw.finish(y0 + w, w, P);
+    if (y0 + w < sw.ny) sw.finish(y0 + w, w, P);  // wave-uniform
+}
+
+template <class T, int RW, bool WALLS, int MODE>
+__global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typename T::A> I)
+{
+    __shared__ typename T::A2 lpsi[RW + 4][64];
+    __shared__ typename T::A2 lrho[RW + 4][64];
+    __shared__ double red[RW][NDIAG];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    tile_body<T, RW, WALLS, MODE>(I, strip, chunk, lpsi, lrho, acc);
     if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
         block_reduce<RW>(acc, red, I.partials + (int64_t)b * NDIAG);
 }
@@ -644,6 +713,144 @@ __global__ __launch_bounds__(256) void init_kernel(Inst<typename T::S, typename 
             else
                 *dst = (typename T::S)feq;
         }
+}
+
+// ------------------------------------------------------------- batching
+//
+// Persistent batch: many instances (any sizes, periodic or walls, sweep or
+// stacked tiling, one storage type) advance in ONE cooperative launch.  Each
+// global step every workgroup walks the item table (instance, tile) with a
+// grid stride and runs exactly the per-site code of the single-instance
+// kernels, then all workgroups meet at a grid barrier before the next step
+// (the next step reads halos written by other workgroups, and overwrites the
+// copy they were reading).  Instances with fewer steps drop out early.
+
+// Grid barrier for a cooperative (co-resident) grid.  Every lane fences at
+// agent scope so its stores are visible to other XCDs' L2 before arriving,
+// and after leaving so later loads see the other workgroups' stores.  The
+// wait is bounded: after ~2^26 sleeps the barrier reports failure through
+// ctl->err and every workgroup leaves the kernel.
+__device__ __forceinline__ bool grid_barrier(BatchCtl* ctl)
+{
+    __shared__ int ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = 1;
+        const uint32_t n = gridDim.x;
+        const uint32_t g = __hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived =
+            __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == n - 1) {
+            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 26) ||
+                    __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+            }
+        }
+        ok = good;
+    }
+    __syncthreads();
+    __threadfence();
+    return ok != 0;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void batch_kernel(
+    const BatchInst<typename T::S, typename T::A>* __restrict__ insts,
+    const BatchItem* __restrict__ items, int nitems, int64_t max_steps, BatchCtl* ctl)
+{
+    using S = typename T::S;
+    using A = typename T::A;
+    using A2 = typename T::A2;
+    __shared__ A2 lpsi[6][256];
+    __shared__ A2 lrho[6][256];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t s = 0; s < max_steps; ++s) {
+        for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
+            const BatchItem it = items[k];
+            const BatchInst<S, A>& bi = insts[it.inst];
+            if (s >= bi.steps) continue;  // uniform: this instance is done
+            Inst<S, A> I = bi.I;
+            if (s & 1) {
+                const S* a = I.fin;
+                I.fin = I.fout;
+                I.fout = const_cast<S*>(a);
+            }
+            I.t += s;
+            const int strip = it.tile / I.nchunks, chunk = it.tile - strip * I.nchunks;
+            if (bi.stacked) {
+                auto lp = reinterpret_cast<A2(*)[64]>(&lpsi[0][0]);
+                auto lr = reinterpret_cast<A2(*)[64]>(&lrho[0][0]);
+                if (I.g.walls)
+                    tile_body<T, 4, true, M_STEP>(I, strip, chunk, lp, lr, acc);
+                else
+                    tile_body<T, 4, false, M_STEP>(I, strip, chunk, lp, lr, acc);
+            } else {
+                if (I.g.walls) {
+                    Sweep<T, 4, true, M_STEP> sw(I, strip, lpsi, lrho, acc);
+                    sw.run(chunk);
+                } else {
+                    Sweep<T, 4, false, M_STEP> sw(I, strip, lpsi, lrho, acc);
+                    sw.run(chunk);
+                }
+            }
+            __syncthreads();  // the next item reuses the LDS ring
+        }
+        if (!grid_barrier(ctl)) return;
+    }
+}
+
+template <class T>
+static int batch_grid_t()
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<T>, 256, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+int batch_grid(int storage)
+{
+    switch (storage) {
+    case 0: return batch_grid_t<TF64>();
+    case 1: return batch_grid_t<TF32>();
+    case 2: return batch_grid_t<TF16>();
+    }
+    return 0;
+}
+
+template <class T>
+static hipError_t batch_go(const void* insts, const BatchItem* items, int nitems,
+                           int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st)
+{
+    auto bi = static_cast<const BatchInst<typename T::S, typename T::A>*>(insts);
+    void* args[] = {(void*)&bi, (void*)&items, (void*)&nitems, (void*)&max_steps, (void*)&ctl};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&batch_kernel<T>), dim3(grid),
+                                      dim3(256), args, 0, st);
+}
+
+hipError_t launch_batch(int storage, const void* insts, const BatchItem* items, int nitems,
+                        int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st)
+{
+    switch (storage) {
+    case 0: return batch_go<TF64>(insts, items, nitems, max_steps, ctl, grid, st);
+    case 1: return batch_go<TF32>(insts, items, nitems, max_steps, ctl, grid, st);
+    case 2: return batch_go<TF16>(insts, items, nitems, max_steps, ctl, grid, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------- launchers

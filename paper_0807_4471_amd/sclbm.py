@@ -62,7 +62,8 @@ class Diag(ctypes.Structure):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("stacked", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("stacked", ctypes.c_int32),
+                ("throttle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SclbmError(RuntimeError):
@@ -85,6 +86,7 @@ def _load():
     pd = ctypes.POINTER(Desc)
     sig = {
         "sclbm_abi_version": ([], i32),
+        "sclbm_selftest": ([], i32),
         "sclbm_strerror": ([i32], ctypes.c_char_p),
         "sclbm_last_error": ([], ctypes.c_char_p),
         "sclbm_state_bytes": ([pd], sz),
@@ -107,6 +109,7 @@ def _load():
         "sclbm_batch_plan": ([ctypes.POINTER(vp), i32, ctypes.POINTER(Tiling), vp, sz, vp,
                               ctypes.POINTER(vp)], i32),
         "sclbm_batch_step": ([vp, ctypes.POINTER(i64), vp], i32),
+        "sclbm_batch_status": ([vp, vp], i32),
         "sclbm_batch_release": ([vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -162,7 +165,10 @@ def _dptr(t):
 class Simulation:
     """One lattice whose state lives in a caller-owned (torch) device buffer."""
 
-    def __init__(self, nx: int, ny: int, device="cuda", buffer=None, **kw):
+    def __init__(self, nx: int, ny: int, device="cuda", buffer=None, tiling=None, **kw):
+        """tiling: None (library default), "auto" (the autotuner's table for
+        this architecture, if it has an entry or a nearby size), or a tuple
+        (tile_x, tile_y, waves[, stacked[, throttle]])."""
         import torch
         self.desc = make_desc(nx, ny, **kw)
         self.nx, self.ny = int(nx), int(ny)
@@ -179,6 +185,14 @@ class Simulation:
         self._h = ctypes.c_void_p()
         check(lib.sclbm_bind(ctypes.byref(self.desc), _dptr(self.buf), nbytes,
                              ctypes.byref(self._h)), "bind")
+        if tiling == "auto":
+            from . import autotune
+            inv_s = {v: k for k, v in STORAGE.items()}
+            inv_b = {v: k for k, v in BOUNDARY.items()}
+            tiling = autotune.tiling_for(self.nx, self.ny, inv_s[self.desc.storage],
+                                         inv_b[self.desc.boundary])
+        if tiling is not None:
+            self.set_tiling(*tiling)
 
     # ------------------------------------------------------------------ life
     def close(self):
@@ -227,14 +241,15 @@ class Simulation:
         check(lib.sclbm_time(self._h, ctypes.byref(v)), "time")
         return v.value
 
-    def set_tiling(self, tile_x: int, tile_y: int, waves: int, stacked: int = 0):
-        t = Tiling(int(tile_x), int(tile_y), int(waves), int(stacked))
+    def set_tiling(self, tile_x: int, tile_y: int, waves: int, stacked: int = 0,
+                   throttle: int = 0):
+        t = Tiling(int(tile_x), int(tile_y), int(waves), int(stacked), int(throttle), 0)
         check(lib.sclbm_set_tiling(self._h, ctypes.byref(t)), "set_tiling")
 
     def get_tiling(self):
         t = Tiling()
         check(lib.sclbm_get_tiling(self._h, ctypes.byref(t)), "get_tiling")
-        return (t.tile_x, t.tile_y, t.waves, t.stacked)
+        return (t.tile_x, t.tile_y, t.waves, t.stacked, t.throttle)
 
     # ------------------------------------------------------------------ read
     def moments_device(self, stream=None):
@@ -279,3 +294,59 @@ class Simulation:
         buf = ctypes.create_string_buffer(data, len(data))
         check(lib.sclbm_restore(self._h, buf, len(data), _stream(stream)), "restore")
         return self
+
+
+def default_batch_tiling(nx: int, ny: int) -> tuple:
+    """A 4-wave tiling usable inside a batch: stacked tiles for small
+    lattices, 252-wide sweep strips otherwise."""
+    if nx * ny <= (1 << 20):
+        ns = -(-nx // 60)
+        return (max(min(-(-nx // ns), 60), min(32, nx)), 4, 4, 1, 0)
+    ns = -(-nx // 252)
+    W = max(-(-nx // ns), min(32, nx))
+    return (W, max(4, min(ny, 128)), 4, 0, 1)
+
+
+class Batch:
+    """Many Simulations (same storage) advanced together in one persistent
+    launch per `step` call.  Each instance's result is bitwise equal to
+    stepping it alone."""
+
+    def __init__(self, sims, tilings=None, stream=None):
+        import torch
+        self.sims = list(sims)
+        n = len(self.sims)
+        if tilings is None:
+            tilings = [default_batch_tiling(s.nx, s.ny) for s in self.sims]
+        self.tilings = [tuple(t) for t in tilings]
+        self._arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.sims])
+        self._tl = (Tiling * n)(*[Tiling(*t) for t in self.tilings])
+        nbytes = int(lib.sclbm_batch_bytes(self._arr, n, self._tl))
+        if nbytes == 0:
+            raise SclbmError(EINVAL, "batch_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.sims[0].buf.device)
+        self._h = ctypes.c_void_p()
+        check(lib.sclbm_batch_plan(self._arr, n, self._tl, _dptr(self.ws), nbytes,
+                                   _stream(stream), ctypes.byref(self._h)), "batch_plan")
+
+    def step(self, steps, stream=None):
+        n = len(self.sims)
+        if isinstance(steps, int):
+            steps = [steps] * n
+        arr = (ctypes.c_int64 * n)(*[int(v) for v in steps])
+        check(lib.sclbm_batch_step(self._h, arr, _stream(stream)), "batch_step")
+        return self
+
+    def status(self, stream=None):
+        check(lib.sclbm_batch_status(self._h, _stream(stream)), "batch_status")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib.sclbm_batch_release(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -30,6 +30,11 @@ def test_every_declared_symbol_is_exported(L):
     assert not missing, missing
 
 
+def test_index_selftest(L):
+    """Row folding used by the kernels: every staged row lands in the lattice."""
+    assert L.lib.sclbm_selftest() == 0
+
+
 def test_version_and_strerror(L):
     assert L.lib.sclbm_abi_version() == 1
     for code in (0, -1, -2, -3, -4, -5, -6):
@@ -86,13 +91,14 @@ def test_bind_errors_and_state(L):
         assert (t.stacked == 0 and t.waves in (1, 2, 4) and t.tile_x <= 64 * t.waves - 4) or \
             (t.stacked == 1 and t.waves in (4, 8) and t.tile_x <= 60)
         for bad in [(61, 8, 1, 0), (60, 8, 3, 0), (20, 8, 1, 0), (60, 3, 1, 0), (253, 8, 4, 0),
-                    (60, 8, 4, 1), (61, 8, 8, 1), (60, 8, 2, 1), (60, 8, 8, 2)]:
+                    (60, 8, 4, 1), (61, 8, 8, 1), (60, 8, 2, 1), (60, 8, 8, 2),
+                    (60, 8, 1, 0, 2), (60, 8, 1, 0, 0, 1)]:
             tb = L.Tiling(*bad)
             assert L.lib.sclbm_set_tiling(h, ctypes.byref(tb)) == L.EINVAL, bad
         ok = L.Tiling(100, 8, 2, 0)
         assert L.lib.sclbm_set_tiling(h, ctypes.byref(ok)) == L.OK
         assert L.lib.sclbm_get_tiling(h, ctypes.byref(t)) == L.OK
-        assert (t.tile_x, t.tile_y, t.waves, t.stacked) == (100, 8, 2, 0)
+        assert (t.tile_x, t.tile_y, t.waves, t.stacked, t.throttle) == (100, 8, 2, 0, 0)
         ok = L.Tiling(50, 8, 8, 1)
         assert L.lib.sclbm_set_tiling(h, ctypes.byref(ok)) == L.OK
         v = ctypes.c_int64(-5)

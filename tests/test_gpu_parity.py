@@ -159,3 +159,19 @@ def test_init_with_velocity_f64():
     _, _, ref = oracle_run(nx, ny, 15, ux=ux, uy=uy, **WORKLOAD)
     e = max_err(m, ref)
     assert e["rho"] <= 1e-12 and e["u"] <= 1e-12, e
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("ny", [2, 3, 4, 5, 9])
+@pytest.mark.parametrize("tiling", [None, (7, 4, 4, 1), (7, 8, 8, 1), (7, 4, 1, 0)])
+def test_walls_short_lattices_all_tilings(storage, ny, tiling):
+    """Walls on lattices no taller than a stacked tile: every staged row must
+    fold into the lattice (regression: rows beyond one mirror image)."""
+    nx = 7
+    kw = dict(WORKLOAD, boundary="walls", wall_u=(0.01, 0.04))
+    banner(f"{storage} walls {nx}x{ny} tiling={tiling}")
+    _, m = gpu_run(nx, ny, 12, storage=storage, tiling=tiling, **kw)
+    _, _, ref = oracle_run(nx, ny, 12, **kw)
+    e = max_err(m, ref)
+    tol = {"f64": 1e-12, "f32": 1e-4, "f16dev": 1e-2}[storage]
+    assert e["rho"] <= tol, e

@@ -244,6 +244,13 @@ int32_t sclbm_batch_step(sclbm_batch* batch, const int64_t* steps, void* hip_str
  * (results of that launch are then invalid), else OK. */
 int32_t sclbm_batch_status(sclbm_batch* batch, void* hip_stream);
 
+/* Launch shape of a planned batch: out[0] = workgroups of this kernel kind
+ * that are co-resident on the device (occupancy x compute units), out[1] =
+ * tiles per step, out[2] = kernel kind (0: all stacked tiles, 1: all sweep
+ * strips, 2: both).  The persistent grid is min(out[0], out[1]) workgroups.
+ * Tile-shape tuners size their tiles from out[0].  Host only. */
+int32_t sclbm_batch_info(const sclbm_batch* batch, int32_t out[3]);
+
 /* Free the batch handle (not the workspace or the instances). */
 int32_t sclbm_batch_release(sclbm_batch* batch);
 

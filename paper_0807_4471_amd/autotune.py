@@ -11,7 +11,13 @@ GPU architecture (``tuning/<arch>.json`` next to this file), which
 of the same storage and boundary, scaled to the lattice.
 
 Batch tilings (``batch=True``) are restricted to what one persistent batch
-launch accepts: 4 waves, stacked tiles or sweep strips.
+launch accepts: 4 waves, stacked tiles or sweep strips.  A batch is tuned as
+a whole (``tune_batch``): each instance's own best tile (timed alone) is
+one candidate policy; the others are "balanced" sweep strips whose chunk
+heights give every tile about the same number of sites, sized so the
+co-resident grid takes 1, 2, 3, 4 or 6 tiles per step.  The winning policy
+(not the tiles of one particular mix) is stored per storage type and applied
+to any mix by ``batch_tilings``.
 
     python -m paper_0807_4471_amd.autotune --sizes 512 1024 4096 --storage f32
 """
@@ -152,6 +158,127 @@ def tiling_for(nx: int, ny: int, storage: str = "f32", boundary: str = "periodic
     Wn = _strip_width(nx, 64 * waves - 4)
     Hn = max(4, min(ny, round(H * ny / ty)))
     return (Wn, Hn, waves, 0, throttle)
+
+
+def policy_key(storage: str) -> str:
+    return f"batch-policy/{storage}"
+
+
+def balanced_tilings(shapes, capacity: int, per_wg: int = 1, throttle: int = 0) -> list:
+    """4-wave sweep strips (<= 252 columns) whose chunks hold about
+    total_sites / (capacity * per_wg) sites each."""
+    shapes = list(shapes)
+    total = sum(nx * ny for nx, ny in shapes)
+    target = max(1.0, total / float(max(1, capacity * per_wg)))
+    out = []
+    for nx, ny in shapes:
+        W = _strip_width(nx, 252)
+        H = int(round(target / W))
+        H = max(min(4, ny), min(ny, H))
+        out.append((W, H, 4, 0, throttle))
+    return out
+
+
+_capacity_cache = {}
+
+
+def batch_capacity(sims, kind: int = 1) -> int:
+    """Co-resident workgroups of the batch kernel of this storage and kind
+    (0 stacked, 1 sweep, 2 both), from a throwaway plan."""
+    from . import sclbm
+    key_ = (sims[0].storage, kind)
+    if key_ not in _capacity_cache:
+        s = sims[0]
+        if kind == 0:
+            tl = [(min(_strip_width(s.nx, 60), 60), 4, 4, 1, 0)]
+        else:
+            tl = [(_strip_width(s.nx, 252), max(min(4, s.ny), min(s.ny, 16)), 4, 0, 0)]
+        b = sclbm.Batch([s], tl)
+        _capacity_cache[key_] = b.info()["capacity"]
+        b.close()
+    return _capacity_cache[key_]
+
+
+def batch_tilings(sims, table: dict | None = None) -> list:
+    """Tilings for a batch of Simulations (one storage type) under the tuned
+    policy; without a policy, each instance's own batch entry (or default)."""
+    from . import sclbm
+    table = load_table() if table is None else table
+    pol = table.get(policy_key(sims[0].storage))
+    if pol and pol.get("policy") == "balanced":
+        cap = batch_capacity(sims, kind=1)
+        return balanced_tilings([(s.nx, s.ny) for s in sims], cap, pol["per_wg"],
+                                pol["throttle"])
+    out = []
+    for s in sims:
+        t = tiling_for(s.nx, s.ny, s.storage, s.boundary, batch=True, table=table)
+        out.append(tuple(t) if t is not None else sclbm.default_batch_tiling(s.nx, s.ny))
+    return out
+
+
+def _time_batch(sims, tilings, steps: int, repeats: int = 3) -> float:
+    """Median milliseconds of `steps` steps of one persistent launch."""
+    import torch
+    from . import sclbm
+    b = sclbm.Batch(sims, tilings)
+    b.step(max(2, steps // 10))
+    times = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    b.status()
+    b.close()
+    return statistics.median(times)
+
+
+def batch_candidates(sims, table: dict) -> list:
+    """(policy record, tilings) pairs in a fixed order."""
+    from . import sclbm
+    out = []
+    own = []
+    for s in sims:
+        t = tiling_for(s.nx, s.ny, s.storage, s.boundary, batch=True, table=table)
+        own.append(tuple(t) if t is not None else sclbm.default_batch_tiling(s.nx, s.ny))
+    out.append(({"policy": "table"}, own))
+    cap = batch_capacity(sims, kind=1)
+    shapes = [(s.nx, s.ny) for s in sims]
+    for per_wg in (1, 2, 3, 4, 6, 8):
+        for th in (0, 1):
+            out.append(({"policy": "balanced", "per_wg": per_wg, "throttle": th},
+                        balanced_tilings(shapes, cap, per_wg, th)))
+    return out
+
+
+def tune_batch(sims, steps: int | None = None, table: dict | None = None, verbose=False) -> dict:
+    """Time every candidate policy on this batch; store the fastest as the
+    policy of the batch's storage type and return its record."""
+    own_table = table is None
+    if own_table:
+        table = load_table()
+    sites = sum(s.nx * s.ny for s in sims)
+    if steps is None:  # about 20 ms per measurement at ~30 GLUPS
+        steps = int(min(2000, max(10, 6e8 / sites)))
+    results = []
+    for pol, tl in batch_candidates(sims, table):
+        ms = _time_batch(sims, tl, steps)
+        results.append((ms, pol))
+        if verbose:
+            print(f"  batch policy {pol}: {ms / steps * 1e3:9.2f} us/step  "
+                  f"{sites * steps / ms / 1e3:9.1f} MLUPS", flush=True)
+    best_ms, best = min(results, key=lambda r: r[0])
+    rec = dict(best)
+    rec.update({"us_per_step": round(best_ms / steps * 1e3, 3),
+                "mlups": round(sites * steps / best_ms / 1e3, 1),
+                "instances": len(sims), "sites": sites, "candidates": len(results)})
+    table[policy_key(sims[0].storage)] = rec
+    if own_table:
+        save_table(table)
+    return rec
 
 
 def main():

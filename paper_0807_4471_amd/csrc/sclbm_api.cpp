@@ -645,7 +645,7 @@ int32_t sclbm_restore(sclbm_inst* h, const void* host_buf, size_t bytes, void* s
 // ------------------------------------------------------------------ batching
 
 struct sclbm_batch {
-    int n = 0, storage = 0, nitems = 0, grid = 0;
+    int n = 0, storage = 0, nitems = 0, grid = 0, kind = 0, capacity = 0;
     std::vector<sclbm_inst*> insts;
     std::vector<sclbm_tiling> tl;
     char* ws = nullptr;
@@ -746,13 +746,18 @@ int32_t sclbm_batch_plan(sclbm_inst* const* insts, int32_t n, const sclbm_tiling
         return fail(SCLBM_EINVAL, "workspace NULL or not 256-byte aligned");
     if (bytes < total) return fail(SCLBM_ESIZE, "workspace of %zu bytes < %zu needed", bytes, total);
     const int storage = insts[0]->d.storage;
-    const int grid = batch_grid(storage);
+    int nstacked = 0;
+    for (int k = 0; k < n; ++k) nstacked += tiling[k].stacked != 0;
+    const int kind = nstacked == n ? B_STACKED : nstacked == 0 ? B_SWEEP : B_MIXED;
+    const int grid = batch_grid(storage, kind);
     if (grid <= 0) return fail(SCLBM_EDEVICE, "cannot size the cooperative grid");
     sclbm_batch* b = new (std::nothrow) sclbm_batch();
     if (!b) return fail(SCLBM_EINVAL, "out of host memory");
     b->n = n;
     b->storage = storage;
+    b->kind = kind;
     b->nitems = ni;
+    b->capacity = grid;
     b->grid = std::min(grid, ni);
     b->insts.assign(insts, insts + n);
     b->tl.assign(tiling, tiling + n);
@@ -813,7 +818,8 @@ int32_t sclbm_batch_step(sclbm_batch* b, const int64_t* steps, void* stream)
     if (e == hipSuccess) e = hipEventRecord(b->uploaded, st);
     if (e == hipSuccess) e = hipMemsetAsync(b->ws + b->off_ctl, 0, sizeof(BatchCtl), st);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
-    e = launch_batch(b->storage, b->ws, reinterpret_cast<const BatchItem*>(b->ws + b->off_items),
+    e = launch_batch(b->storage, b->kind, b->ws,
+                     reinterpret_cast<const BatchItem*>(b->ws + b->off_items),
                      b->nitems, max_steps, reinterpret_cast<BatchCtl*>(b->ws + b->off_ctl),
                      b->grid, st);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
@@ -823,6 +829,15 @@ int32_t sclbm_batch_step(sclbm_batch* b, const int64_t* steps, void* stream)
         h->cur ^= (int)(steps[k] & 1);
         if (h->d.boundary == SCLBM_WALLS_Y) h->wall_steps += steps[k];
     }
+    return SCLBM_OK;
+}
+
+int32_t sclbm_batch_info(const sclbm_batch* b, int32_t out[3])
+{
+    if (!b || !out) return fail(SCLBM_EINVAL, "NULL argument");
+    out[0] = b->capacity;
+    out[1] = b->nitems;
+    out[2] = b->kind;
     return SCLBM_OK;
 }
 

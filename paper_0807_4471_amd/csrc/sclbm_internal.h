@@ -114,10 +114,14 @@ __host__ __device__ inline int fold_row(int r, int ny, bool walls)
 hipError_t launch_sweep(int storage, int cw, int mode, const void* inst, int nblocks,
                         hipStream_t st);
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
-// Largest co-resident grid of the batch kernel for this storage (0 on error).
-int batch_grid(int storage);
-hipError_t launch_batch(int storage, const void* insts, const BatchItem* items, int nitems,
-                        int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st);
+// Tile paths a batch kernel holds: stacked tiles, sweep strips, or both.
+enum { B_STACKED = 0, B_SWEEP = 1, B_MIXED = 2 };
+
+// Largest co-resident grid of the batch kernel of this storage and kind, 0 on
+// error.
+int batch_grid(int storage, int kind);
+hipError_t launch_batch(int storage, int kind, const void* insts, const BatchItem* items,
+                        int nitems, int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st);
 hipError_t launch_init(int storage, const void* inst, const double* rhoA, const double* rhoB,
                        const double* ux, const double* uy, int random, uint64_t seed,
                        double meanA, double meanB, double amp, hipStream_t st);

@@ -1,6 +1,6 @@
 """Per-kernel, per-grid-size duration summary of a rocprofv3 database.
 
-    python profiles/summarize_kernels.py <run_results.db> [name-substring]
+    python -m paper_0807_4471_amd.profsummary <run_results.db> [name-substring]
 
 Groups dispatches by (kernel name, grid size, workgroup size) so launches of
 one kernel template on different lattices are not averaged together.

@@ -111,6 +111,7 @@ def _load():
         "sclbm_batch_step": ([vp, ctypes.POINTER(i64), vp], i32),
         "sclbm_batch_status": ([vp, vp], i32),
         "sclbm_batch_release": ([vp], i32),
+        "sclbm_batch_info": ([vp, ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -187,10 +188,7 @@ class Simulation:
                              ctypes.byref(self._h)), "bind")
         if tiling == "auto":
             from . import autotune
-            inv_s = {v: k for k, v in STORAGE.items()}
-            inv_b = {v: k for k, v in BOUNDARY.items()}
-            tiling = autotune.tiling_for(self.nx, self.ny, inv_s[self.desc.storage],
-                                         inv_b[self.desc.boundary])
+            tiling = autotune.tiling_for(self.nx, self.ny, self.storage, self.boundary)
         if tiling is not None:
             self.set_tiling(*tiling)
 
@@ -205,6 +203,14 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+    @property
+    def storage(self) -> str:
+        return {v: k for k, v in STORAGE.items()}[self.desc.storage]
+
+    @property
+    def boundary(self) -> str:
+        return {v: k for k, v in BOUNDARY.items()}[self.desc.boundary]
 
     @property
     def handle(self):
@@ -318,6 +324,11 @@ class Batch:
         n = len(self.sims)
         if tilings is None:
             tilings = [default_batch_tiling(s.nx, s.ny) for s in self.sims]
+        elif isinstance(tilings, str):
+            if tilings != "auto":
+                raise ValueError("tilings: None, 'auto' or a list of 5-tuples")
+            from . import autotune
+            tilings = autotune.batch_tilings(self.sims)
         self.tilings = [tuple(t) for t in tilings]
         self._arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.sims])
         self._tl = (Tiling * n)(*[Tiling(*t) for t in self.tilings])
@@ -339,6 +350,14 @@ class Batch:
 
     def status(self, stream=None):
         check(lib.sclbm_batch_status(self._h, _stream(stream)), "batch_status")
+
+    def info(self) -> dict:
+        """capacity: co-resident workgroups of this kernel kind; tiles per
+        step; kind (0 stacked, 1 sweep, 2 both); grid actually launched."""
+        out = (ctypes.c_int32 * 3)()
+        check(lib.sclbm_batch_info(self._h, out), "batch_info")
+        return {"capacity": out[0], "tiles": out[1], "kind": out[2],
+                "grid": min(out[0], out[1])}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -1,0 +1,37 @@
+"""Host-side pieces of the serving loop: the seeded request trace and the
+latency/throughput summary (no GPU)."""
+import math
+
+import numpy as np
+
+from paper_0807_4471_amd import serving
+
+
+def test_trace_is_seeded_and_in_range():
+    a = serving.make_trace(500, rate=10.0, seed=4242)
+    b = serving.make_trace(500, rate=10.0, seed=4242)
+    assert [(r.arrival, r.nx, r.steps, r.storage, r.boundary, r.seed) for r in a] == \
+           [(r.arrival, r.nx, r.steps, r.storage, r.boundary, r.seed) for r in b]
+    assert all(64 <= r.nx <= 1024 and r.nx == r.ny for r in a)
+    assert all(1000 <= r.steps <= 100000 for r in a)
+    assert {r.storage for r in a} == {"f32", "f16dev"}
+    assert {r.boundary for r in a} == {"periodic", "walls"}
+    assert all((r.wall_u in (0.01, 0.05, 0.1)) == (r.boundary == "walls") for r in a)
+    arr = np.array([r.arrival for r in a])
+    assert np.all(np.diff(arr) > 0)
+    # Poisson: mean gap 1/rate
+    assert abs(np.diff(arr).mean() - 0.1) < 0.02
+    # log-uniform sizes: median near the geometric mean of the range
+    assert abs(math.log(np.median([r.nx for r in a])) - math.log(256)) < 0.25
+
+
+def test_summary_percentiles():
+    trace = [serving.Request(rid=i, arrival=float(i), nx=10, ny=10, steps=100) for i in range(100)]
+    res = {i: serving.Result(i, float(i), float(i), float(i) + 1.0 + 0.01 * i, "ok", None, None)
+           for i in range(100)}
+    res[5].status = "failed"
+    out = serving.summarize(trace, res, makespan=200.0, busy=50.0)
+    assert out["completed"] == 100 and out["failed"] == 1
+    assert abs(out["p50_latency_s"] - (1.0 + 0.01 * 49.5)) < 1e-9
+    assert out["p99_latency_s"] > 1.98
+    assert abs(out["aggregate_mlups"] - 100 * 100 * 100 / 200.0 / 1e6) < 1e-12

@@ -2,22 +2,39 @@
 """Throughput benchmark of the fused two-species Shan-Chen LBM step on one
 MI355X.
 
-Headline workload: the micro-emulsion lattice, 512x512 periodic, FP32
-populations, caption couplings (G_A1=-12.55, G_A2=11.70, G_B1=-11.80,
+Headline workload (`value`): the micro-emulsion lattice, 512x512 periodic,
+FP32 populations, caption couplings (G_A1=-12.55, G_A2=11.70, G_B1=-11.80,
 G_B2=10.95, G^X=0.58), rho0 = 0.70, Psi = rho0 (1 - exp(-rho/rho0)),
 tau_A = tau_B = 1, densities 0.7 (1 + 0.05 U) from seed 1, fused FP64
-diagnostics every 1000 steps.  One step = one fused stream + force +
-collide pass over the lattice (plus the diagnostics reduction on every
-1000th step).  Inputs are resident in HBM before timing starts.
+diagnostics every 1000 steps, tile shape from the tuned table.  One step =
+one fused stream + force + collide pass over the lattice (plus the
+diagnostics reduction on every 1000th step).  Inputs are resident in HBM
+before timing starts; the timed region is bracketed by device syncs and
+timed with HIP events on the launch stream.
 
-Prints ONE JSON line (see the keys below).  `value` is two-species MLUPS
-(1 LUP = one site advanced one step, both species).
+Side objects in the same JSON line:
+  rho0_sweep     FP32 at rho0 in {0.60, 0.70, 0.75}, same steps, against the
+                 FP64 GPU path (mass drift, structure-factor peak)
+  dram_resident  lattices larger than the 256 MiB Infinity Cache
+  batch          64 uneven instances in one persistent launch per call,
+                 against the same instances stepped one launch at a time
+  serving        a Poisson trace served with continuous batching, against
+                 the same trace served one request at a time on the FP64 path
+  roofline       of the step kernel of the headline workload
+  cpu_baseline   the FP64 oracle on the host, on a bounded sample
+
+Prints ONE JSON line.  `value` is two-species MLUPS (1 LUP = one site
+advanced one step, both species).
+
+    python bench.py                      # everything, N = 1
+    python bench.py --calibrate-copy     # plain copy for the counter scale
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -30,6 +47,11 @@ BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72}
 WORKLOAD = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
 KERNEL_SOURCES = ["paper_0807_4471_amd/csrc/sclbm_kernels.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+METRIC = "two-species MLUPS and % HBM roofline; p50/p99 latency of served solves"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -48,30 +70,41 @@ def parse():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--rho0", type=float, default=0.70)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the rho0 sweep")
     ap.add_argument("--no-dram", action="store_true", help="skip the DRAM-resident side runs")
-    ap.add_argument("--cpu-steps", type=int, default=80)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=20000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     return ap.parse_args()
 
 
-def run_gpu(nx, storage, steps, warmup, rho0, diag_every, torch, sclbm):
-    kw = dict(WORKLOAD, rho0=rho0)
-    sim = sclbm.Simulation(nx, nx, storage=storage, diag_every=diag_every,
-                           rho_ref=(0.7, 0.7), **kw)
-    sim.init_random(1, mean=(0.7, 0.7), amp=0.05)
-    d0 = sim.diagnostics()
-    sim.step(warmup)
-    torch.cuda.synchronize()
+def timed(torch, fn):
+    """HIP-event milliseconds of fn() on the current stream, plus wall s."""
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(st)
-    sim.step(steps)
+    fn()
     e1.record(st)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
+    return e0.elapsed_time(e1), time.perf_counter() - t0
+
+
+def run_gpu(nx, storage, steps, warmup, rho0, diag_every, torch, sclbm, tiling="auto"):
+    kw = dict(WORKLOAD, rho0=rho0)
+    sim = sclbm.Simulation(nx, nx, storage=storage, diag_every=diag_every,
+                           rho_ref=(0.7, 0.7), tiling=tiling, **kw)
+    sim.init_random(1, mean=(0.7, 0.7), amp=0.05)
+    d0 = sim.diagnostics()
+    sim.step(warmup)
+    ms_total, wall = timed(torch, lambda: sim.step(steps))
     d = sim.diagnostics()
     d["mass0"] = d0["mass"]
     return sim, ms_total, wall, d
@@ -81,7 +114,8 @@ def roofline(nx, storage, kernel_ms):
     """Roofline of the fused step kernel.  kernel_ms is its average launch
     duration: the HIP-event time of the timed region on the launch stream
     divided by the number of step launches (the launches run back to back;
-    the few diagnostics reductions inside the region add < 0.1%)."""
+    the diagnostics reductions inside the region add < 0.1%).  Algorithmic
+    bytes: every site reads and writes 18 populations once."""
     alg = BYTES_PER_LUP[storage] * nx * nx
     achieved = alg / (kernel_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -90,8 +124,9 @@ def roofline(nx, storage, kernel_ms):
 
 
 def traffic_for(key: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+    """Bytes per launch between L2 and the memory fabric, from committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain copy, if they
+    were taken on the current kernel source; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -100,6 +135,118 @@ def traffic_for(key: str):
     if t.get("kernel_hash") != kernel_hash():
         return None
     return t.get("per_launch_bytes", {}).get(key)
+
+
+def structure_peak(torch, sim):
+    """Peak (|k| shell, S) of the radially averaged structure factor of
+    phi = rho_A - rho_B (k in units of 2 pi / L)."""
+    import numpy as np
+    m = sim.moments()
+    phi = m["rhoA"] - m["rhoB"]
+    ny, nx = phi.shape
+    F = np.fft.fft2(phi - phi.mean())
+    S = (np.abs(F) ** 2) / (nx * ny)
+    K = np.sqrt((np.fft.fftfreq(ny) * ny)[:, None] ** 2 + (np.fft.fftfreq(nx) * nx)[None, :] ** 2)
+    shell = np.rint(K).astype(int)
+    tot = np.bincount(shell.ravel(), S.ravel())
+    cnt = np.bincount(shell.ravel())
+    Sk = np.where(cnt > 0, tot / np.maximum(cnt, 1), 0.0)
+    Sk[0] = 0.0
+    k = int(np.argmax(Sk))
+    return {"k_peak": k, "S_peak": float(Sk[k])}
+
+
+def rho0_sweep(a, torch, sclbm, head):
+    out = []
+    for rho0 in (0.60, 0.70, 0.75):
+        row = {"rho0": rho0}
+        for storage in ("f32", "f64"):
+            if storage == a.storage and rho0 == a.rho0 and head is not None:
+                sim, ms, d = head
+            else:
+                sim, ms, _, d = run_gpu(a.nx, storage, a.steps, a.warmup, rho0, 1000, torch,
+                                        sclbm)
+            row[storage] = {
+                "mlups": round(a.nx * a.nx * a.steps / (ms * 1e-3) / 1e6, 1),
+                "mass_drift": [float(abs(d["mass"][s] / d["mass0"][s] - 1.0)) for s in (0, 1)],
+                "nonfinite_sites": int(d["bad_sites"]),
+                **structure_peak(torch, sim)}
+            if sim is not (head[0] if head else None):
+                sim.close()
+        out.append(row)
+        log(f"sweep rho0={rho0}: {row}")
+    return {"steps": a.warmup + a.steps, "reference": "FP64 GPU path (matches the oracle to 1e-10 "
+            "at 1000 steps; trajectories decorrelate later, so peaks are compared)",
+            "runs": out}
+
+
+def batch_mix(seed=2026, n=64):
+    """Uneven instances: sizes from {128..512}^2, rho0 ~ U(0.60, 0.80),
+    G^X ~ U(0.50, 0.65), tau_s ~ U(0.8, 1.2); instance i seeded 1000 + i."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sides = rng.choice([128, 192, 256, 384, 512], size=n)
+    rho0 = rng.uniform(0.60, 0.80, n)
+    gx = rng.uniform(0.50, 0.65, n)
+    tau = rng.uniform(0.8, 1.2, (n, 2))
+    return [dict(nx=int(sides[i]), ny=int(sides[i]), rho0=float(rho0[i]), Gx=float(gx[i]),
+                 tau=(float(tau[i, 0]), float(tau[i, 1])), seed=1000 + i) for i in range(n)]
+
+
+def run_batch(a, torch, sclbm):
+    mix = batch_mix()
+    sites = sum(m["nx"] * m["ny"] for m in mix)
+
+    def make(tiling=None):
+        sims = []
+        for m in mix:
+            kw = dict(WORKLOAD, rho0=m["rho0"], Gx=m["Gx"], tau=m["tau"])
+            s = sclbm.Simulation(m["nx"], m["ny"], storage="f32", tiling=tiling, **kw)
+            s.init_random(m["seed"])
+            sims.append(s)
+        return sims
+
+    sims = make()
+    b = sclbm.Batch(sims, "auto")
+    info = b.info()
+    ms_b, _ = timed(torch, lambda: b.step(a.batch_steps))
+    b.status()
+    b.close()
+    seq = make(tiling="auto")
+    ms_s, _ = timed(torch, lambda: [s.step(a.batch_steps) for s in seq])
+    same = all(torch.equal(x.buf[:x.nbytes], y.buf[:y.nbytes]) for x, y in zip(sims, seq))
+    bad = sum(1 for s in sims if s.diagnostics()["bad_sites"] > 0)
+    for s in sims + seq:
+        s.close()
+    del sims, seq
+    torch.cuda.empty_cache()
+    out = {"workload": "64 uneven FP32 instances (128^2..512^2, rho0~U(0.6,0.8), "
+                       "G^X~U(0.5,0.65), tau_s~U(0.8,1.2)), one persistent launch",
+           "instances": len(mix), "sites": sites, "steps": a.batch_steps,
+           "batched_mlups": round(sites * a.batch_steps / (ms_b * 1e-3) / 1e6, 1),
+           "sequential_mlups": round(sites * a.batch_steps / (ms_s * 1e-3) / 1e6, 1),
+           "speedup": round(ms_s / ms_b, 3), "bitwise_equal_to_sequential": bool(same),
+           "instances_nonfinite": bad, "plan": info}
+    log(f"batch: {out}")
+    return out
+
+
+def run_serving(a, torch, sclbm, rate_lups):
+    from paper_0807_4471_amd import serving
+    side, steps = (64, 1024), (1000, 100000)
+    e_sites = (side[1] ** 2 - side[0] ** 2) / (2.0 * math.log(side[1] / side[0]))
+    e_steps = (steps[1] - steps[0]) / math.log(steps[1] / steps[0])
+    rate = a.serve_load * rate_lups / (e_sites * e_steps)
+    trace = serving.make_trace(a.serve_requests, rate=rate, seed=4242, side=side, steps=steps)
+    srv = serving.Server(keep_moments=False)
+    r = serving.summarize_public(srv.run(trace))
+    log(f"serving (batched): {r}")
+    r64 = serving.summarize_public(serving.serve_sequential_f64(trace))
+    log(f"serving (sequential FP64): {r64}")
+    return {"workload": f"{a.serve_requests} Poisson requests at {rate:.3f}/s "
+                        f"(load {a.serve_load} of {rate_lups / 1e9:.1f} GLUPS), sizes 64^2..1024^2 "
+                        "and steps 1e3..1e5 log-uniform, f32 or f16dev, half sheared walls",
+            "arrival_rate_per_s": round(rate, 4), "batched": r, "sequential_f64": r64}
 
 
 def cpu_baseline(nx, steps, rho0):
@@ -119,6 +266,17 @@ def cpu_baseline(nx, steps, rho0):
                       f"{steps} steps ({dt:.1f} s, single thread)"}
 
 
+def calibrate_copy(torch):
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -127,10 +285,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_0807_4471_amd import sclbm
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
+    if a.calibrate_copy:
+        calibrate_copy(torch)
+        return
+    from paper_0807_4471_amd import sclbm
     nx, storage = a.nx, a.storage
     sim, ms_total, wall, d = run_gpu(nx, storage, a.steps, a.warmup, a.rho0, 1000, torch, sclbm)
     ms_step = ms_total / a.steps
@@ -140,7 +301,7 @@ def main():
     # ping-pong footprint (2 copies x 18 populations) vs the 256 MiB Infinity Cache
     roof["cache_resident"] = BYTES_PER_LUP[storage] * nx * nx < 256 * 2 ** 20
     out = {
-        "metric": "two-species MLUPS and % HBM roofline; p50/p99 latency of served solves",
+        "metric": METRIC,
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -161,7 +322,12 @@ def main():
         "mass_drift": [float(abs(d["mass"][s] / d["mass0"][s] - 1.0)) for s in (0, 1)],
         "wall_s": round(wall, 3),
     }
+    log(f"headline: {out['value']} MLUPS, {roof['kernel_us']} us/step, frac {roof['frac']}")
+    if not a.no_sweep:
+        out["rho0_sweep"] = rho0_sweep(a, torch, sclbm, (sim, ms_total, d))
+    sim.close()
     del sim
+    torch.cuda.empty_cache()
     if not a.no_dram:
         side = []
         for st_, n_ in (("f32", 4096), ("f16dev", 4096), ("f64", 2048)):
@@ -171,9 +337,17 @@ def main():
             side.append({"workload": f"{n_}x{n_} {st_} (DRAM-resident)",
                          "mlups": round(n_ * n_ / (mt / 200 * 1e-3) / 1e6, 1), "roofline": r,
                          "tiling": list(s2.get_tiling())})
+            log(f"dram: {side[-1]}")
+            s2.close()
             del s2
             torch.cuda.empty_cache()
         out["dram_resident"] = side
+    rate_lups = 2.0e10
+    if not a.no_batch:
+        out["batch"] = run_batch(a, torch, sclbm)
+        rate_lups = out["batch"]["batched_mlups"] * 1e6
+    if not a.no_serve:
+        out["serving"] = run_serving(a, torch, sclbm, rate_lups)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, a.cpu_steps, a.rho0)
     print(json.dumps(out), flush=True)

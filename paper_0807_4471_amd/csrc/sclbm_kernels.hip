@@ -90,15 +90,27 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t species_rsrc(const char* base,
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, nrec, 0x00020000);
 }
 
+// Cache-policy bits of the population loads and stores (gfx950 CPol: 1 sc0,
+// 2 nt, 16 sc1).
+#ifndef SCLBM_LOAD_CPOL
+#define SCLBM_LOAD_CPOL 0
+#endif
+#ifndef SCLBM_STORE_CPOL
+#define SCLBM_STORE_CPOL 0
+#endif
+
 template <class S>
 __device__ __forceinline__ S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff)
 {
     if constexpr (sizeof(S) == 8)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+        return __builtin_bit_cast(
+            S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, SCLBM_LOAD_CPOL));
     else if constexpr (sizeof(S) == 4)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+        return __builtin_bit_cast(
+            S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, SCLBM_LOAD_CPOL));
     else
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0));
+        return __builtin_bit_cast(
+            S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, SCLBM_LOAD_CPOL));
 }
 
 template <class S>
@@ -106,11 +118,14 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 {
     if constexpr (sizeof(S) == 8) {
         typedef unsigned u2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0,
+                                              SCLBM_STORE_CPOL);
     } else if constexpr (sizeof(S) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0,
+                                              SCLBM_STORE_CPOL);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, 0,
+                                              SCLBM_STORE_CPOL);
     }
 }
 

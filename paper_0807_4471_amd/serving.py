@@ -123,11 +123,11 @@ class Server:
         self.tiling = tiling
         self.rate_lups = 2.0e10  # running estimate of batch throughput (LUP/s)
 
-    def _batch_tiling(self, req: Request):
+    def _batch_tilings(self, sims):
         from . import autotune, sclbm
-        t = autotune.tiling_for(req.nx, req.ny, req.storage, req.boundary, batch=True) \
-            if self.tiling == "auto" else None
-        return t if t is not None else sclbm.default_batch_tiling(req.nx, req.ny)
+        if self.tiling == "auto":
+            return autotune.batch_tilings(sims)
+        return [sclbm.default_batch_tiling(s.nx, s.ny) for s in sims]
 
     def run(self, trace: list[Request], on_event=None, on_admit=None) -> dict:
         """Serve the trace in real time; returns results and metrics.
@@ -180,8 +180,7 @@ class Server:
                     if storage in plans:
                         plans[storage][1].close()
                     sims = [active[r][1] for r in rids]
-                    tl = [self._batch_tiling(active[r][0]) for r in rids]
-                    plans[storage] = (keyset, sclbm.Batch(sims, tl), rids)
+                    plans[storage] = (keyset, sclbm.Batch(sims, self._batch_tilings(sims)), rids)
                 _, batch, order = plans[storage]
                 steps = [min(active[r][2], chunk) for r in order]
                 batch.step(steps)
@@ -244,6 +243,12 @@ def serve_sequential_f64(trace: list[Request], device="cuda", keep_moments=False
                                   "ok" if d["bad_sites"] == 0 else "failed", mom, d)
         sim.close()
     return summarize(trace, results, time.perf_counter() - t0, busy)
+
+
+def summarize_public(s: dict) -> dict:
+    """The metrics of `summarize` without the per-request results."""
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()
+            if k != "results"}
 
 
 def summarize(trace, results: dict, makespan: float, busy: float) -> dict:

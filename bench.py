@@ -32,7 +32,6 @@ advanced one step, both species).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -45,7 +44,6 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72}
 WORKLOAD = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
-KERNEL_SOURCES = ["paper_0807_4471_amd/csrc/sclbm_kernels.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 METRIC = "two-species MLUPS and % HBM roofline; p50/p99 latency of served solves"
 
@@ -55,11 +53,8 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_0807_4471_amd.build import kernel_source_hash
+    return kernel_source_hash()
 
 
 def parse():

@@ -26,6 +26,16 @@ FLAGS = [
 ]
 
 
+def kernel_source_hash() -> str:
+    """Short hash of the kernel source: identifies the code that profiles and
+    counter figures were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(CSRC, "sclbm_kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     objs = []
     t0 = time.time()

@@ -1,15 +1,35 @@
-"""Per-kernel, per-grid-size duration summary of a rocprofv3 database.
+"""Summaries of rocprofv3 output for the step kernels.
 
-    python -m paper_0807_4471_amd.profsummary <run_results.db> [name-substring]
+    python -m paper_0807_4471_amd.profsummary db <run_results.db> [name-substring]
+    python -m paper_0807_4471_amd.profsummary stats <kernel_stats.csv> [name-substring]
+    python -m paper_0807_4471_amd.profsummary traffic \\
+        --fetch <FETCH_SIZE counter_collection.csv> --write <WRITE_SIZE ...csv> \\
+        --copy-fetch <csv> --copy-write <csv> --copy-bytes 1073741824 \\
+        --entry KEY=NAME_SUBSTRING@GRID [...] -o traffic_counters.json
 
-Groups dispatches by (kernel name, grid size, workgroup size) so launches of
-one kernel template on different lattices are not averaged together.
+`db` groups the dispatches of a rocpd database by (kernel name, grid size,
+workgroup size), so launches of one kernel template on different lattices
+are not averaged together.  `stats` prints a kernel_stats.csv in microseconds.
+
+`traffic` turns two counter runs (FETCH_SIZE, then WRITE_SIZE: KiB moved
+between L2 and the memory fabric per dispatch) into bytes per launch of the
+kernels named by the --entry options.  Each counter is scaled by what it
+reads for a plain device copy of --copy-bytes bytes (the largest dispatch in
+the copy runs), so the figures are in true bytes whatever the counter's own
+unit.  The output records the hash of the kernel source the counters were
+taken on; readers treat the figures as stale once the source changes.
 """
+from __future__ import annotations
+
+import argparse
+import csv
+import json
 import sqlite3
 import sys
+from collections import defaultdict
 
 
-def main(db, sub=""):
+def cmd_db(db, sub=""):
     c = sqlite3.connect(db)
     q = ("select name, grid_x, workgroup_x, count(*), avg(duration), min(duration), "
          "max(duration), vgpr_count, accum_vgpr_count, sgpr_count, lds_size "
@@ -24,5 +44,87 @@ def main(db, sub=""):
               f"{mx / 1e3:9.3f} {v:4d} {a:4d} {s:4d} {lds}")
 
 
+def cmd_stats(path, sub=""):
+    print(f"| kernel | calls | avg us | min us | max us | share % |")
+    print(f"|---|---:|---:|---:|---:|---:|")
+    for r in csv.DictReader(open(path)):
+        if sub and sub not in r["Name"]:
+            continue
+        short = r["Name"].replace("sclbm::", "").split("(")[0]
+        print(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
+              f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
+              f"{float(r['Percentage']):.2f} |")
+
+
+def _per_dispatch(path):
+    """{(kernel name, grid size): [counter value per dispatch]}"""
+    out = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        out[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return out
+
+
+def _copy_factor(path, nbytes):
+    vals = [v for vs in _per_dispatch(path).values() for v in vs]
+    top = max(vals)
+    return nbytes / (top * 1024.0), top
+
+
+def _match(table, spec):
+    sub, grid = spec.rsplit("@", 1)
+    hits = [(k, v) for k, v in table.items() if sub in k[0] and k[1] == int(grid)]
+    if len(hits) != 1:
+        raise SystemExit(f"entry {spec!r} matches {len(hits)} kernels")
+    return hits[0]
+
+
+def cmd_traffic(argv):
+    ap = argparse.ArgumentParser(prog="profsummary traffic")
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--entry", action="append", required=True, help="KEY=NAME_SUBSTRING@GRID")
+    ap.add_argument("-o", "--out", required=True)
+    a = ap.parse_args(argv)
+    from .build import kernel_source_hash
+    ff, fraw = _copy_factor(a.copy_fetch, a.copy_bytes)
+    fw, wraw = _copy_factor(a.copy_write, a.copy_bytes)
+    fetch, write = _per_dispatch(a.fetch), _per_dispatch(a.write)
+    res = {"kernel_hash": kernel_source_hash(),
+           "calibration": {"copy_bytes": a.copy_bytes, "copy_fetch_kib": fraw,
+                           "copy_write_kib": wraw, "fetch_factor": ff, "write_factor": fw},
+           "per_launch_bytes": {}, "detail": {}}
+    for e in a.entry:
+        key, spec = e.split("=", 1)
+        (name, grid), fv = _match(fetch, spec)
+        (_, _), wv = _match(write, spec)
+        fb = sum(fv) / len(fv) * 1024.0 * ff
+        wb = sum(wv) / len(wv) * 1024.0 * fw
+        res["per_launch_bytes"][key] = round(fb + wb)
+        res["detail"][key] = {"kernel": name.split("(")[0], "grid": grid,
+                              "dispatches": [len(fv), len(wv)],
+                              "fetch_bytes": round(fb), "write_bytes": round(wb)}
+    with open(a.out, "w") as fh:
+        json.dump(res, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(res, indent=1, sort_keys=True))
+
+
+def main(argv):
+    if not argv:
+        raise SystemExit(__doc__)
+    cmd, rest = argv[0], argv[1:]
+    if cmd == "db":
+        cmd_db(*rest)
+    elif cmd == "stats":
+        cmd_stats(*rest)
+    elif cmd == "traffic":
+        cmd_traffic(rest)
+    else:
+        raise SystemExit(__doc__)
+
+
 if __name__ == "__main__":
-    main(*sys.argv[1:])
+    main(sys.argv[1:])

@@ -16,6 +16,9 @@ Side objects in the same JSON line:
   rho0_sweep     FP32 at rho0 in {0.60, 0.70, 0.75}, same steps, against the
                  FP64 GPU path (mass drift, structure-factor peak)
   dram_resident  lattices larger than the 256 MiB Infinity Cache
+  sheared_cell   1024x1024 between walls (top at U = 0.01, 0.05, 0.1):
+                 mean shear stress and apparent viscosity, FP32 and FP16
+                 storage against the FP64 path
   batch          64 uneven instances in one persistent launch per call,
                  against the same instances stepped one launch at a time
   serving        a Poisson trace served with continuous batching, against
@@ -67,6 +70,8 @@ def parse():
     ap.add_argument("--rho0", type=float, default=0.70)
     ap.add_argument("--no-sweep", action="store_true", help="skip the rho0 sweep")
     ap.add_argument("--no-dram", action="store_true", help="skip the DRAM-resident side runs")
+    ap.add_argument("--no-shear", action="store_true", help="skip the sheared-cell object")
+    ap.add_argument("--shear-steps", type=int, default=50000)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
@@ -173,6 +178,44 @@ def rho0_sweep(a, torch, sclbm, head):
     return {"steps": a.warmup + a.steps, "reference": "FP64 GPU path (matches the oracle to 1e-10 "
             "at 1000 steps; trajectories decorrelate later, so peaks are compared)",
             "runs": out}
+
+
+def sheared_cell(a, torch, sclbm):
+    """1024x1024 two-species cell between a resting bottom wall and a top wall
+    moving at U, random start, in FP64, FP32 and FP16-deviation storage:
+    mean shear stress on the moving wall over the last 10% of the steps and
+    the apparent viscosity at the end, FP32/FP16 against the FP64 path."""
+    from paper_0807_4471_amd.observables import shear_observables
+    n, steps = 1024, a.shear_steps
+    last = max(1, steps // 10)
+    runs = []
+    for U in (0.01, 0.05, 0.1):
+        row = {"U": U}
+        for storage in ("f64", "f32", "f16dev"):
+            sim = sclbm.Simulation(n, n, storage=storage, boundary="walls", wall_u=(0.0, U),
+                                   rho_ref=(0.7, 0.7), tiling="auto", **WORKLOAD)
+            sim.init_random(1)
+
+            def go():
+                sim.step(steps - last)
+                sim.reset_wall_accum()
+                sim.step(last)
+            ms, _ = timed(torch, go)
+            obs = shear_observables(sim)
+            obs["mlups"] = round(n * n * steps / (ms * 1e-3) / 1e6, 1)
+            row[storage] = obs
+            sim.close()
+        for storage in ("f32", "f16dev"):
+            for k in ("wall_stress", "eta_app"):
+                ref = row["f64"][k]
+                row[storage][k + "_rel_err"] = abs(row[storage][k] - ref) / abs(ref)
+        runs.append(row)
+        log(f"shear U={U}: {row}")
+    torch.cuda.empty_cache()
+    return {"workload": f"{n}x{n} sheared cell, top wall at U, caption couplings, rho0=0.70, "
+                        f"5% random start, {steps} steps; stress over the last {last}",
+            "reference": "FP64 GPU path (matches the oracle to <= 2.1e-11 in both observables "
+                         "on 128x64 x 2000 steps)", "runs": runs}
 
 
 def batch_mix(seed=2026, n=64):
@@ -337,6 +380,8 @@ def main():
             del s2
             torch.cuda.empty_cache()
         out["dram_resident"] = side
+    if not a.no_shear:
+        out["sheared_cell"] = sheared_cell(a, torch, sclbm)
     rate_lups = 2.0e10
     if not a.no_batch:
         out["batch"] = run_batch(a, torch, sclbm)

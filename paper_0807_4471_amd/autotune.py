@@ -15,9 +15,13 @@ launch accepts: 4 waves, stacked tiles or sweep strips.  A batch is tuned as
 a whole (``tune_batch``): each instance's own best tile (timed alone) is
 one candidate policy; the others are "balanced" sweep strips whose chunk
 heights give every tile about the same number of sites, sized so the
-co-resident grid takes 1, 2, 3, 4 or 6 tiles per step.  The winning policy
-(not the tiles of one particular mix) is stored per storage type and applied
-to any mix by ``batch_tilings``.
+co-resident grid takes 1..8 tiles per step, with a floor on the chunk
+height (short chunks re-read their 4 halo rows too often when a batch holds
+few sites).  Policies are scored on several mixes at once (geometric mean
+of each mix's time relative to its best policy), so the winner suits large
+and small batches alike.  The winning policy (not the tiles of one
+particular mix) is stored per storage type and applied to any mix by
+``batch_tilings``.
 
     python -m paper_0807_4471_amd.autotune --sizes 512 1024 4096 --storage f32
 """
@@ -164,16 +168,17 @@ def policy_key(storage: str) -> str:
     return f"batch-policy/{storage}"
 
 
-def balanced_tilings(shapes, capacity: int, per_wg: int = 1, throttle: int = 0) -> list:
+def balanced_tilings(shapes, capacity: int, per_wg: int = 1, throttle: int = 0,
+                     hmin: int = 4) -> list:
     """4-wave sweep strips (<= 252 columns) whose chunks hold about
-    total_sites / (capacity * per_wg) sites each."""
+    total_sites / (capacity * per_wg) sites each, and at least hmin rows."""
     shapes = list(shapes)
     total = sum(nx * ny for nx, ny in shapes)
     target = max(1.0, total / float(max(1, capacity * per_wg)))
     out = []
     for nx, ny in shapes:
         W = _strip_width(nx, 252)
-        H = int(round(target / W))
+        H = max(int(round(target / W)), hmin)
         H = max(min(4, ny), min(ny, H))
         out.append((W, H, 4, 0, throttle))
     return out
@@ -208,7 +213,7 @@ def batch_tilings(sims, table: dict | None = None) -> list:
     if pol and pol.get("policy") == "balanced":
         cap = batch_capacity(sims, kind=1)
         return balanced_tilings([(s.nx, s.ny) for s in sims], cap, pol["per_wg"],
-                                pol["throttle"])
+                                pol["throttle"], pol.get("hmin", 4))
     out = []
     for s in sims:
         t = tiling_for(s.nx, s.ny, s.storage, s.boundary, batch=True, table=table)
@@ -236,46 +241,63 @@ def _time_batch(sims, tilings, steps: int, repeats: int = 3) -> float:
     return statistics.median(times)
 
 
-def batch_candidates(sims, table: dict) -> list:
-    """(policy record, tilings) pairs in a fixed order."""
-    from . import sclbm
-    out = []
-    own = []
-    for s in sims:
-        t = tiling_for(s.nx, s.ny, s.storage, s.boundary, batch=True, table=table)
-        own.append(tuple(t) if t is not None else sclbm.default_batch_tiling(s.nx, s.ny))
-    out.append(({"policy": "table"}, own))
-    cap = batch_capacity(sims, kind=1)
-    shapes = [(s.nx, s.ny) for s in sims]
-    for per_wg in (1, 2, 3, 4, 6, 8):
-        for th in (0, 1):
-            out.append(({"policy": "balanced", "per_wg": per_wg, "throttle": th},
-                        balanced_tilings(shapes, cap, per_wg, th)))
+def batch_policies() -> list:
+    """Candidate batch policies in a fixed order."""
+    out = [{"policy": "table"}]
+    for hmin in (4, 8, 16, 32):
+        for per_wg in (1, 2, 3, 4, 6, 8):
+            for th in (0, 1):
+                out.append({"policy": "balanced", "per_wg": per_wg, "throttle": th,
+                            "hmin": hmin})
     return out
 
 
-def tune_batch(sims, steps: int | None = None, table: dict | None = None, verbose=False) -> dict:
-    """Time every candidate policy on this batch; store the fastest as the
-    policy of the batch's storage type and return its record."""
+def policy_tilings(sims, pol: dict, table: dict) -> list:
+    from . import sclbm
+    if pol["policy"] == "balanced":
+        return balanced_tilings([(s.nx, s.ny) for s in sims], batch_capacity(sims, kind=1),
+                                pol["per_wg"], pol["throttle"], pol.get("hmin", 4))
+    out = []
+    for s in sims:
+        t = tiling_for(s.nx, s.ny, s.storage, s.boundary, batch=True, table=table)
+        out.append(tuple(t) if t is not None else sclbm.default_batch_tiling(s.nx, s.ny))
+    return out
+
+
+def tune_batch(mixes, steps: int | None = None, table: dict | None = None,
+               verbose=False) -> dict:
+    """Time every candidate policy on each mix (a list of Simulation lists of
+    one storage type); store the policy with the best geometric-mean time
+    relative to each mix's fastest as that storage type's batch policy."""
+    import math
+    if mixes and not isinstance(mixes[0], (list, tuple)):
+        mixes = [mixes]
     own_table = table is None
     if own_table:
         table = load_table()
-    sites = sum(s.nx * s.ny for s in sims)
-    if steps is None:  # about 20 ms per measurement at ~30 GLUPS
-        steps = int(min(2000, max(10, 6e8 / sites)))
-    results = []
-    for pol, tl in batch_candidates(sims, table):
-        ms = _time_batch(sims, tl, steps)
-        results.append((ms, pol))
-        if verbose:
-            print(f"  batch policy {pol}: {ms / steps * 1e3:9.2f} us/step  "
-                  f"{sites * steps / ms / 1e3:9.1f} MLUPS", flush=True)
-    best_ms, best = min(results, key=lambda r: r[0])
-    rec = dict(best)
-    rec.update({"us_per_step": round(best_ms / steps * 1e3, 3),
-                "mlups": round(sites * steps / best_ms / 1e3, 1),
-                "instances": len(sims), "sites": sites, "candidates": len(results)})
-    table[policy_key(sims[0].storage)] = rec
+    pols = batch_policies()
+    times = []            # [mix][policy] us per step
+    for sims in mixes:
+        sites = sum(s.nx * s.ny for s in sims)
+        n = steps if steps is not None else int(min(2000, max(10, 6e8 / sites)))
+        row = []
+        for pol in pols:
+            ms = _time_batch(sims, policy_tilings(sims, pol, table), n)
+            row.append(ms / n * 1e3)
+            if verbose:
+                print(f"  [{len(sims)} inst, {sites} sites] {pol}: {row[-1]:9.2f} us/step  "
+                      f"{sites / row[-1]:9.1f} MLUPS", flush=True)
+        times.append(row)
+    score = [math.exp(sum(math.log(times[m][p] / min(times[m])) for m in range(len(mixes)))
+                      / len(mixes)) for p in range(len(pols))]
+    best = min(range(len(pols)), key=lambda p: score[p])
+    rec = dict(pols[best])
+    rec.update({"score": round(score[best], 4), "candidates": len(pols),
+                "mixes": [{"instances": len(sims), "sites": sum(s.nx * s.ny for s in sims),
+                           "us_per_step": round(times[m][best], 3),
+                           "best_us_per_step": round(min(times[m]), 3)}
+                          for m, sims in enumerate(mixes)]})
+    table[policy_key(mixes[0][0].storage)] = rec
     if own_table:
         save_table(table)
     return rec

@@ -790,7 +790,9 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl)
 // one, so more workgroups are co-resident.  Workgroup b takes items b, b + G,
 // b + 2G, ... of the (instance-major, tile-major) item table, so the
 // workgroups in flight at any moment work on neighbouring tiles of few
-// instances (their halo rows meet in L2, their pages in the TLB).
+// instances (their halo rows meet in L2, their pages in the TLB).  (Giving
+// each XCD a contiguous range of the items in flight, as the single-instance
+// kernels do, measured no better here.)
 template <class T, int KIND>
 __global__ __launch_bounds__(256) void batch_kernel(
     const BatchInst<typename T::S, typename T::A>* __restrict__ insts,

@@ -143,6 +143,8 @@ class Server:
         t0 = time.perf_counter()
         busy = 0.0
         plans = {}           # storage -> (frozenset(rids), Batch)
+        nchunks = nplans = 0
+        active_sum = 0
         while pi < len(pending) or active:
             now = time.perf_counter() - t0
             # admission, FIFO
@@ -181,6 +183,7 @@ class Server:
                         plans[storage][1].close()
                     sims = [active[r][1] for r in rids]
                     plans[storage] = (keyset, sclbm.Batch(sims, self._batch_tilings(sims)), rids)
+                    nplans += 1
                 _, batch, order = plans[storage]
                 steps = [min(active[r][2], chunk) for r in order]
                 batch.step(steps)
@@ -190,6 +193,8 @@ class Server:
             torch.cuda.synchronize()
             dt = time.perf_counter() - tc
             busy += dt
+            nchunks += 1
+            active_sum += len(active)
             if dt > 0 and work > 0:
                 self.rate_lups = 0.7 * self.rate_lups + 0.3 * (work / dt)
             # retire finished requests
@@ -213,7 +218,10 @@ class Server:
         makespan = time.perf_counter() - t0
         for st in plans:
             plans[st][1].close()
-        return summarize(trace, results, makespan, busy)
+        out = summarize(trace, results, makespan, busy)
+        out.update({"chunks": nchunks, "plans_built": nplans,
+                    "mean_active": active_sum / max(1, nchunks)})
+        return out
 
 
 def serve_sequential_f64(trace: list[Request], device="cuda", keep_moments=False) -> dict:

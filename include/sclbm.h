@@ -113,11 +113,15 @@ typedef struct {
  *   stores have completed before it stages the next row (fewer memory
  *   requests in flight, which suits DRAM-resident lattices); 0 lets stores
  *   overlap the following rows.
+ * write_through = 1 (stacked tiles only) writes the populations through the
+ *   L2 (system-coherent stores) instead of leaving them dirty there until
+ *   the end of the step: faster when the state stays in the Infinity Cache
+ *   (small lattices), slower when it streams from HBM.  0 otherwise.
  * Always tile_x >= min(32, nx).  The result of a step does not depend on
  * the tiling (bit for bit). */
 typedef struct {
     int32_t tile_x, tile_y, waves, stacked;
-    int32_t throttle, reserved;
+    int32_t throttle, write_through;
 } sclbm_tiling;
 
 typedef struct sclbm_inst sclbm_inst;     /* opaque host handle: one lattice  */

@@ -67,10 +67,13 @@ def _strip_width(nx: int, wmax: int) -> int:
 
 
 def candidates(nx: int, ny: int, batch: bool = False) -> list:
-    """Tilings (tile_x, tile_y, waves, stacked, throttle) in a fixed order."""
+    """Tilings (tile_x, tile_y, waves, stacked, throttle[, write_through]) in
+    a fixed order."""
     out = []
     for rw in ((4,) if batch else (4, 8)):
         out.append((min(_strip_width(nx, 60), 60), rw, rw, 1, 0))
+        if not batch:
+            out.append((min(_strip_width(nx, 60), 60), rw, rw, 1, 0, 1))
     for cw in ((4,) if batch else (1, 2, 4)):
         W = _strip_width(nx, 64 * cw - 4)
         ns = -(-nx // W)
@@ -156,9 +159,11 @@ def tiling_for(nx: int, ny: int, storage: str = "f32", boundary: str = "periodic
             best = (d, tx, ty, v["tiling"])
     if best is None:
         return None
-    _, tx, ty, (W, H, waves, stacked, throttle) = best
+    _, tx, ty, t = best
+    W, H, waves, stacked, throttle = t[:5]
+    wt = t[5] if len(t) > 5 else 0
     if stacked:
-        return (min(_strip_width(nx, 60), 60), H, waves, 1, throttle)
+        return (min(_strip_width(nx, 60), 60), H, waves, 1, throttle, wt)
     Wn = _strip_width(nx, 64 * waves - 4)
     Hn = max(4, min(ny, round(H * ny / ty)))
     return (Wn, Hn, waves, 0, throttle)

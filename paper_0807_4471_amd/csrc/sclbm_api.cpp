@@ -190,14 +190,17 @@ struct sclbm_inst {
     int cw, W, H, nstrips, nchunks;
     int stacked;          // 1: tile mode, cw waves stacked along y (H == cw)
     int throttle;         // sweep iterations wait for the previous row's stores
+    int wt;               // stacked tiles: write-through population stores
 };
 
 namespace {
 
-void set_tiling(sclbm_inst* h, int cw, int W, int H, int stacked = 0, int throttle = 0)
+void set_tiling(sclbm_inst* h, int cw, int W, int H, int stacked = 0, int throttle = 0,
+                int wt = 0)
 {
     h->stacked = stacked;
     h->throttle = throttle;
+    h->wt = wt;
     h->cw = cw;
     h->W = W;
     h->H = H;
@@ -252,7 +255,7 @@ Inst<S, A> make_inst(const sclbm_inst* h, const Coef<A>& c, int from, int to, in
 // Launch one sweep in `mode` with the given tiling; for READ mode `out`
 // holds the five output pointers.
 int32_t sweep(sclbm_inst* h, int mode, int cw, int W, int H, int from, int to,
-              double* const* out, hipStream_t st, int* nblocks)
+              double* const* out, hipStream_t st, int* nblocks, int wt = 0)
 {
     hipError_t e;
     int nb = 0;
@@ -260,7 +263,7 @@ int32_t sweep(sclbm_inst* h, int mode, int cw, int W, int H, int from, int to,
         if (out)
             for (int k = 0; k < 5; ++k) I.out[k] = out[k];
         nb = I.nstrips * I.nchunks;
-        return launch_sweep(h->d.storage, cw, mode, &I, nb, st);
+        return launch_sweep(h->d.storage, cw, wt, mode, &I, nb, st);
     };
     if (h->d.storage == SCLBM_F64) {
         auto I = make_inst<double, double>(h, h->cd, from, to, W, H);
@@ -452,7 +455,7 @@ int32_t sclbm_step(sclbm_inst* h, int64_t n, void* stream)
         const bool diag = h->d.diag_every > 0 && h->t % h->d.diag_every == 0;
         int nb = 0;
         int32_t rc = sweep(h, diag ? M_STEP_DIAG : M_STEP, h->stacked ? -h->cw : h->cw, h->W,
-                           h->H, h->cur, 1 - h->cur, nullptr, st, &nb);
+                           h->H, h->cur, 1 - h->cur, nullptr, st, &nb, h->stacked ? h->wt : 0);
         if (rc) return rc;
         if (diag) {
             hipError_t e = launch_reduce(reinterpret_cast<double*>(h->buf + h->L.off_partials),
@@ -474,7 +477,10 @@ int32_t sclbm_set_tiling(sclbm_inst* h, const sclbm_tiling* tl)
     const int cw = tl->waves, W = tl->tile_x, H = tl->tile_y;
     if (tl->stacked != 0 && tl->stacked != 1) return fail(SCLBM_EINVAL, "stacked must be 0 or 1");
     if (tl->throttle != 0 && tl->throttle != 1) return fail(SCLBM_EINVAL, "throttle must be 0 or 1");
-    if (tl->reserved != 0) return fail(SCLBM_EINVAL, "reserved must be 0");
+    if (tl->write_through != 0 && tl->write_through != 1)
+        return fail(SCLBM_EINVAL, "write_through must be 0 or 1");
+    if (tl->write_through && !tl->stacked)
+        return fail(SCLBM_EINVAL, "write_through needs stacked tiles");
     if (tl->stacked) {
         if (cw != 4 && cw != 8) return fail(SCLBM_EINVAL, "stacked tiles need waves 4 or 8");
         if (H != cw) return fail(SCLBM_EINVAL, "stacked tiles need tile_y == waves");
@@ -485,7 +491,7 @@ int32_t sclbm_set_tiling(sclbm_inst* h, const sclbm_tiling* tl)
         if (H < std::min(MIN_TILE_Y, h->d.ny)) return fail(SCLBM_EINVAL, "tile_y %d too small", H);
     }
     if (W < std::min(MIN_TILE_X, h->d.nx)) return fail(SCLBM_EINVAL, "tile_x %d too small", W);
-    set_tiling(h, cw, W, H, tl->stacked, tl->throttle);
+    set_tiling(h, cw, W, H, tl->stacked, tl->throttle, tl->write_through);
     return SCLBM_OK;
 }
 
@@ -497,7 +503,7 @@ int32_t sclbm_get_tiling(const sclbm_inst* h, sclbm_tiling* out)
     out->waves = h->cw;
     out->stacked = h->stacked;
     out->throttle = h->throttle;
-    out->reserved = 0;
+    out->write_through = h->wt;
     return SCLBM_OK;
 }
 
@@ -667,8 +673,8 @@ size_t batch_inst_size(int storage)
 
 int32_t check_batch_tiling(const sclbm_inst* h, const sclbm_tiling& t)
 {
-    if ((t.throttle != 0 && t.throttle != 1) || t.reserved != 0)
-        return fail(SCLBM_EINVAL, "throttle must be 0 or 1, reserved 0");
+    if ((t.throttle != 0 && t.throttle != 1) || t.write_through != 0)
+        return fail(SCLBM_EINVAL, "batch tilings: throttle 0 or 1, write_through 0");
     if (t.waves != 4) return fail(SCLBM_EINVAL, "batch tilings need waves == 4");
     if (t.stacked) {
         if (t.tile_y != 4 || t.tile_x > 60)

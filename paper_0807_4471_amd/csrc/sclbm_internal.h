@@ -111,7 +111,9 @@ __host__ __device__ inline int fold_row(int r, int ny, bool walls)
 }
 
 // Host-side launchers (defined in sclbm_kernels.hip).
-hipError_t launch_sweep(int storage, int cw, int mode, const void* inst, int nblocks,
+// cw > 0: sweep strips cw waves wide; cw < 0: stacked tiles of -cw waves,
+// with write-through population stores if wt.
+hipError_t launch_sweep(int storage, int cw, int wt, int mode, const void* inst, int nblocks,
                         hipStream_t st);
 hipError_t launch_reduce(const double* partials, int nblocks, double* out, hipStream_t st);
 // Tile paths a batch kernel holds: stacked tiles, sweep strips, or both.

@@ -90,42 +90,38 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t species_rsrc(const char* base,
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, nrec, 0x00020000);
 }
 
-// Cache-policy bits of the population loads and stores (gfx950 CPol: 1 sc0,
-// 2 nt, 16 sc1).
-#ifndef SCLBM_LOAD_CPOL
-#define SCLBM_LOAD_CPOL 0
-#endif
-#ifndef SCLBM_STORE_CPOL
-#define SCLBM_STORE_CPOL 0
-#endif
+// Cache-policy bits of buffer loads and stores (gfx950: 1 sc0, 2 nt, 16 sc1).
+// Population stores either stay in L2 until the end of the kernel (0) or
+// write through it with system coherence (CPOL_WT).
+constexpr int CPOL_WT = 16;
 
 template <class S>
 __device__ __forceinline__ S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff)
 {
     if constexpr (sizeof(S) == 8)
         return __builtin_bit_cast(
-            S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, SCLBM_LOAD_CPOL));
+            S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
     else if constexpr (sizeof(S) == 4)
         return __builtin_bit_cast(
-            S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, SCLBM_LOAD_CPOL));
+            S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
     else
         return __builtin_bit_cast(
-            S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, SCLBM_LOAD_CPOL));
+            S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0));
 }
 
-template <class S>
+template <class S, int CP = 0>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, S v)
 {
     if constexpr (sizeof(S) == 8) {
         typedef unsigned u2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0,
-                                              SCLBM_STORE_CPOL);
+                                              CP);
     } else if constexpr (sizeof(S) == 4) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0,
-                                              SCLBM_STORE_CPOL);
+                                              CP);
     } else {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, 0,
-                                              SCLBM_STORE_CPOL);
+                                              CP);
     }
 }
 
@@ -153,7 +149,7 @@ __device__ __forceinline__ typename T::A expo(typename T::A v)
 // form: rho = rho_ref + sum_i h_i, j = sum_i c_i h_i (the reference carries
 // no momentum), f^eq_i - w_i rho_ref = w_i ((rho - rho_ref) + rho P_i).  Sums
 // of binary16 values are exact in FP32, so the mass bookkeeping is exact.
-template <class T, int CW, bool WALLS, int MODE, int NS = 6>
+template <class T, int CW, bool WALLS, int MODE, int NS = 6, int SCP = 0>
 struct Sweep {
     using S = typename T::S;
     using A = typename T::A;
@@ -455,10 +451,10 @@ struct Sweep {
                     const uint32_t dst = col + (ro_off + (uint32_t)((k - 9 * s) * plane_b));
                     if constexpr (DEV) {
                         const _Float16 h = (_Float16)val;
-                        bstore<_Float16>(rout[s], dst, h);
+                        bstore<_Float16, SCP>(rout[s], dst, h);
                         qsum += (float)h;  // exact: sum of binary16 values
                     } else {
-                        bstore<S>(rout[s], dst, (S)val);
+                        bstore<S, SCP>(rout[s], dst, (S)val);
                     }
                 }
                 if constexpr (DEV) {
@@ -472,9 +468,9 @@ struct Sweep {
                     typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
                     h2_t hv = {(_Float16)0, (_Float16)0};
                     hv = __builtin_amdgcn_cvt_sr_f16_f32(hv, h0, r, false);
-                    bstore<_Float16>(rout[s], sw_ + soff, hv[0]);
+                    bstore<_Float16, SCP>(rout[s], sw_ + soff, hv[0]);
                 } else {
-                    bstore<S>(rout[s], sw_ + soff, (S)f[0]);
+                    bstore<S, SCP>(rout[s], sw_ + soff, (S)f[0]);
                 }
             }
             if constexpr (WALLS) {
@@ -610,14 +606,14 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
 // its populations in registers); waves 0..3 also stage the four halo rows
 // y0-2, y0-1, y0+RW, y0+RW+1; one barrier; every wave finishes its row.  The
 // dependency chain per workgroup is one row instead of H+4 rows.
-template <class T, int RW, bool WALLS, int MODE>
+template <class T, int RW, bool WALLS, int MODE, int SCP = 0>
 __device__ __forceinline__ void tile_body(const Inst<typename T::S, typename T::A>& I, int strip,
                                           int chunk, typename T::A2 (*lpsi)[64],
                                           typename T::A2 (*lrho)[64], double* acc)
 {
     static_assert(RW >= 4, "four waves stage the halo rows");
     using A = typename T::A;
-    Sweep<T, 1, WALLS, MODE, RW + 4> sw(I, strip, lpsi, lrho, acc);
+    Sweep<T, 1, WALLS, MODE, RW + 4, SCP> sw(I, strip, lpsi, lrho, acc);
     const int w = threadIdx.x >> 6;  // uniform per wave
     const int y0 = chunk * RW;
     A P[18];
@@ -636,7 +632,7 @@ __device__ __forceinline__ void tile_body(const Inst<typename T::S, typename T::
     if (y0 + w < sw.ny) sw.finish(y0 + w, w, P);  // wave-uniform
 }
 
-template <class T, int RW, bool WALLS, int MODE>
+template <class T, int RW, bool WALLS, int MODE, int SCP>
 __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typename T::A> I)
 {
     __shared__ typename T::A2 lpsi[RW + 4][64];
@@ -645,7 +641,7 @@ __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typen
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    tile_body<T, RW, WALLS, MODE>(I, strip, chunk, lpsi, lrho, acc);
+    tile_body<T, RW, WALLS, MODE, SCP>(I, strip, chunk, lpsi, lrho, acc);
     if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
         block_reduce<RW>(acc, red, I.partials + (int64_t)b * NDIAG);
 }
@@ -909,10 +905,15 @@ hipError_t launch_batch(int storage, int kind, const void* insts, const BatchIte
 // ---------------------------------------------------------------- launchers
 
 template <class T, int RW, bool WALLS, int MODE>
-static hipError_t go_tile(const void* inst, int nb, hipStream_t st)
+static hipError_t go_tile(int wt, const void* inst, int nb, hipStream_t st)
 {
     const auto& I = *static_cast<const Inst<typename T::S, typename T::A>*>(inst);
-    hipLaunchKernelGGL((tile_kernel<T, RW, WALLS, MODE>), dim3(nb), dim3(64 * RW), 0, st, I);
+    if (wt)
+        hipLaunchKernelGGL((tile_kernel<T, RW, WALLS, MODE, CPOL_WT>), dim3(nb), dim3(64 * RW), 0,
+                           st, I);
+    else
+        hipLaunchKernelGGL((tile_kernel<T, RW, WALLS, MODE, 0>), dim3(nb), dim3(64 * RW), 0, st,
+                           I);
     return hipGetLastError();
 }
 
@@ -937,25 +938,26 @@ static hipError_t go_mode(int mode, const void* inst, int nb, hipStream_t st)
 }
 
 template <class T, bool WALLS>
-static hipError_t go_stacked(int rw, int mode, const void* inst, int nb, hipStream_t st)
+static hipError_t go_stacked(int rw, int wt, int mode, const void* inst, int nb, hipStream_t st)
 {
     if (mode != M_STEP && mode != M_STEP_DIAG) return hipErrorInvalidValue;
     const bool d = mode == M_STEP_DIAG;
     switch (rw) {
-    case 4: return d ? go_tile<T, 4, WALLS, M_STEP_DIAG>(inst, nb, st)
-                     : go_tile<T, 4, WALLS, M_STEP>(inst, nb, st);
-    case 8: return d ? go_tile<T, 8, WALLS, M_STEP_DIAG>(inst, nb, st)
-                     : go_tile<T, 8, WALLS, M_STEP>(inst, nb, st);
+    case 4: return d ? go_tile<T, 4, WALLS, M_STEP_DIAG>(wt, inst, nb, st)
+                     : go_tile<T, 4, WALLS, M_STEP>(wt, inst, nb, st);
+    case 8: return d ? go_tile<T, 8, WALLS, M_STEP_DIAG>(wt, inst, nb, st)
+                     : go_tile<T, 8, WALLS, M_STEP>(wt, inst, nb, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <class T>
-static hipError_t go_cw(int cw, int walls, int mode, const void* inst, int nb, hipStream_t st)
+static hipError_t go_cw(int cw, int wt, int walls, int mode, const void* inst, int nb,
+                        hipStream_t st)
 {
     if (cw < 0)  // stacked tile mode with -cw waves
-        return walls ? go_stacked<T, true>(-cw, mode, inst, nb, st)
-                     : go_stacked<T, false>(-cw, mode, inst, nb, st);
+        return walls ? go_stacked<T, true>(-cw, wt, mode, inst, nb, st)
+                     : go_stacked<T, false>(-cw, wt, mode, inst, nb, st);
     switch (cw) {
     case 1: return walls ? go_mode<T, 1, true>(mode, inst, nb, st)
                          : go_mode<T, 1, false>(mode, inst, nb, st);
@@ -967,14 +969,15 @@ static hipError_t go_cw(int cw, int walls, int mode, const void* inst, int nb, h
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep(int storage, int cw, int mode, const void* inst, int nb, hipStream_t st)
+hipError_t launch_sweep(int storage, int cw, int wt, int mode, const void* inst, int nb,
+                        hipStream_t st)
 {
     // walls flag lives in the Geo at the same offset for every instantiation
     const int walls = static_cast<const Inst<float, float>*>(inst)->g.walls;
     switch (storage) {
-    case 0: return go_cw<TF64>(cw, walls, mode, inst, nb, st);
-    case 1: return go_cw<TF32>(cw, walls, mode, inst, nb, st);
-    case 2: return go_cw<TF16>(cw, walls, mode, inst, nb, st);
+    case 0: return go_cw<TF64>(cw, wt, walls, mode, inst, nb, st);
+    case 1: return go_cw<TF32>(cw, wt, walls, mode, inst, nb, st);
+    case 2: return go_cw<TF16>(cw, wt, walls, mode, inst, nb, st);
     }
     return hipErrorInvalidValue;
 }

@@ -63,7 +63,7 @@ class Diag(ctypes.Structure):
 class Tiling(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("stacked", ctypes.c_int32),
-                ("throttle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("throttle", ctypes.c_int32), ("write_through", ctypes.c_int32)]
 
 
 class SclbmError(RuntimeError):
@@ -248,14 +248,15 @@ class Simulation:
         return v.value
 
     def set_tiling(self, tile_x: int, tile_y: int, waves: int, stacked: int = 0,
-                   throttle: int = 0):
-        t = Tiling(int(tile_x), int(tile_y), int(waves), int(stacked), int(throttle), 0)
+                   throttle: int = 0, write_through: int = 0):
+        t = Tiling(int(tile_x), int(tile_y), int(waves), int(stacked), int(throttle),
+                   int(write_through))
         check(lib.sclbm_set_tiling(self._h, ctypes.byref(t)), "set_tiling")
 
     def get_tiling(self):
         t = Tiling()
         check(lib.sclbm_get_tiling(self._h, ctypes.byref(t)), "get_tiling")
-        return (t.tile_x, t.tile_y, t.waves, t.stacked, t.throttle)
+        return (t.tile_x, t.tile_y, t.waves, t.stacked, t.throttle, t.write_through)
 
     # ------------------------------------------------------------------ read
     def moments_device(self, stream=None):

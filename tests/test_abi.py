@@ -101,6 +101,11 @@ def test_bind_errors_and_state(L):
         assert (t.tile_x, t.tile_y, t.waves, t.stacked, t.throttle) == (100, 8, 2, 0, 0)
         ok = L.Tiling(50, 8, 8, 1)
         assert L.lib.sclbm_set_tiling(h, ctypes.byref(ok)) == L.OK
+        wt = L.Tiling(50, 4, 4, 1, 0, 1)
+        assert L.lib.sclbm_set_tiling(h, ctypes.byref(wt)) == L.OK
+        assert L.lib.sclbm_get_tiling(h, ctypes.byref(t)) == L.OK and t.write_through == 1
+        for bad in [(50, 4, 4, 1, 0, 2), (100, 8, 2, 0, 0, 1)]:
+            assert L.lib.sclbm_set_tiling(h, ctypes.byref(L.Tiling(*bad))) == L.EINVAL, bad
         v = ctypes.c_int64(-5)
         assert L.lib.sclbm_time(h, ctypes.byref(v)) == L.OK
         assert L.lib.sclbm_checkpoint_bytes(h) > 0

@@ -9,8 +9,10 @@ from paper_0807_4471_amd import autotune
 @pytest.mark.parametrize("n", [64, 100, 128, 250, 512, 1000, 4096])
 @pytest.mark.parametrize("batch", [False, True])
 def test_candidates_are_valid(n, batch):
-    for (W, H, waves, stacked, th) in autotune.candidates(n, n, batch):
-        assert th in (0, 1)
+    for c in autotune.candidates(n, n, batch):
+        W, H, waves, stacked, th = c[:5]
+        wt = c[5] if len(c) > 5 else 0
+        assert th in (0, 1) and wt in (0, 1) and (stacked or not wt) and not (batch and wt)
         if stacked:
             assert waves in ((4,) if batch else (4, 8)) and H == waves and W <= 60
         else:

@@ -15,14 +15,15 @@ def _sim(nx, ny, storage, **kw):
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
 def test_tiling_does_not_change_results(storage):
-    """Every tiling (strip width, chunk height, waves per workgroup) gives the
-    same bits: halos and ragged tails are handled exactly."""
+    """Every tiling (strip width, chunk height, waves per workgroup, store
+    throttle, write-through stores) gives the same bits: halos and ragged
+    tails are handled exactly."""
     nx, ny = 200, 90
     banner(f"{storage} tiling invariance {nx}x{ny}")
     ref = None
     for tl in [(60, 8, 1), (33, 17, 1), (124, 8, 2), (100, 45, 2), (200, 90, 4), (252, 8, 4),
                (71, 30, 4), (60, 4, 1), (60, 8, 8, 1), (41, 4, 4, 1), (50, 8, 8, 1),
-               (200, 90, 4, 0, 1), (60, 8, 1, 0, 1)]:
+               (200, 90, 4, 0, 1), (60, 8, 1, 0, 1), (41, 4, 4, 1, 0, 1), (57, 8, 8, 1, 0, 1)]:
         s = _sim(nx, ny, storage)
         s.set_tiling(*tl)
         s.init_random(7)

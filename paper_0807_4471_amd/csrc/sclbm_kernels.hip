@@ -20,9 +20,13 @@
 // barrier sufficient (the slot a lane writes in iteration y+1 is not read in
 // iteration y).
 //
-// Workgroups are dispatched round-robin over the 8 XCDs; blocks are remapped
-// so that each XCD gets a contiguous range of (strip, chunk) tiles, keeping
-// the halo rows shared by vertically adjacent chunks in one L2.
+// Tiles are numbered row-major (all strips of one chunk row, then the next
+// chunk row), and since workgroups are dispatched round-robin over the 8
+// XCDs, blocks are remapped so that each XCD gets a contiguous range of
+// tiles: horizontally adjacent strips, whose edges share cache lines, and
+// most vertically adjacent chunks, which share halo rows, run under one L2.
+// (Strip-major numbering fetched ~12% more than the algorithmic bytes on
+// DRAM-resident lattices and was 5-16% slower.)
 #include <type_traits>
 
 #include "sclbm_internal.h"
@@ -554,7 +558,7 @@ struct Sweep {
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
-// give each XCD a contiguous range of logical tiles.
+// give each XCD a contiguous range of logical (row-major) tiles.
 __device__ __forceinline__ int xcd_remap(int b, int n)
 {
     const int per = n / 8, rem = n % 8, xcd = b % 8, k = b / 8;
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
     __shared__ typename T::A2 lrho[6][64 * CW];
     __shared__ double red[CW][NDIAG];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
+    const int chunk = b / I.nstrips, strip = b - chunk * I.nstrips;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     Sweep<T, CW, WALLS, MODE> sw(I, strip, lpsi, lrho, acc);
     sw.run(chunk);
@@ -639,7 +643,7 @@ __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typen
     __shared__ typename T::A2 lrho[RW + 4][64];
     __shared__ double red[RW][NDIAG];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int strip = b / I.nchunks, chunk = b - strip * I.nchunks;
+    const int chunk = b / I.nstrips, strip = b - chunk * I.nstrips;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     tile_body<T, RW, WALLS, MODE, SCP>(I, strip, chunk, lpsi, lrho, acc);
     if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)

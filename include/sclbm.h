@@ -236,17 +236,32 @@ int32_t sclbm_batch_plan(sclbm_inst* const* insts, int32_t n, const sclbm_tiling
                          void* dev_workspace, size_t bytes, void* hip_stream,
                          sclbm_batch** out);
 
-/* Advance instance k of the batch by steps[k] >= 0 steps in ONE persistent
- * cooperative launch: all workgroups are co-resident and meet at a grid
- * barrier after each step; instances with fewer steps drop out early.  Per
- * site the arithmetic is that of sclbm_step, so each instance's result is
- * bitwise equal to running it alone.  Async; the instances' times advance.
- * A failed barrier (never expected) is reported by sclbm_batch_status. */
+/* Advance instance k of the batch by steps[k] >= 0 steps: in PERSISTENT mode
+ * in ONE cooperative launch (all workgroups co-resident, a grid barrier
+ * after each step), in STEPWISE mode in max_k steps[k] ordinary launches;
+ * instances with fewer steps drop out early.  Per site the arithmetic is
+ * that of sclbm_step, so each instance's result is bitwise equal to running
+ * it alone.  Async; the instances' times advance.  A failed barrier (never
+ * expected) is reported by sclbm_batch_status. */
 int32_t sclbm_batch_step(sclbm_batch* batch, const int64_t* steps, void* hip_stream);
 
 /* Syncs hip_stream; EDEVICE if a grid barrier of the last launch timed out
  * (results of that launch are then invalid), else OK. */
 int32_t sclbm_batch_status(sclbm_batch* batch, void* hip_stream);
+
+/* Execution mode of a batch (sclbm_batch_set_mode).
+ * PERSISTENT (default): each sclbm_batch_step is ONE cooperative launch whose
+ *   co-resident workgroups walk the tile table step after step, meeting at a
+ *   grid barrier after every step.
+ * STEPWISE: each sclbm_batch_step enqueues one ordinary launch per step,
+ *   one workgroup per tile of every instance that still has steps; the
+ *   kernel boundaries order the steps (no grid barrier, full occupancy).
+ * Both give every instance the bits of running it alone. */
+enum { SCLBM_BATCH_PERSISTENT = 0, SCLBM_BATCH_STEPWISE = 1 };
+
+/* Select the execution mode of later sclbm_batch_step calls.  Host only;
+ * EINVAL for an unknown mode. */
+int32_t sclbm_batch_set_mode(sclbm_batch* batch, int32_t mode);
 
 /* Launch shape of a planned batch: out[0] = workgroups of this kernel kind
  * that are co-resident on the device (occupancy x compute units), out[1] =

@@ -21,7 +21,8 @@ few sites).  Policies are scored on several mixes at once (geometric mean
 of each mix's time relative to its best policy), so the winner suits large
 and small batches alike.  The winning policy (not the tiles of one
 particular mix) is stored per storage type and applied to any mix by
-``batch_tilings``.
+``batch_plan``.  Every policy is tried in both execution modes (one
+persistent launch per call, or one ordinary launch per step).
 
     python -m paper_0807_4471_amd.autotune --sizes 512 1024 4096 --storage f32
 """
@@ -209,28 +210,26 @@ def batch_capacity(sims, kind: int = 1) -> int:
     return _capacity_cache[key_]
 
 
-def batch_tilings(sims, table: dict | None = None) -> list:
-    """Tilings for a batch of Simulations (one storage type) under the tuned
-    policy; without a policy, each instance's own batch entry (or default)."""
-    from . import sclbm
+def batch_plan(sims, table: dict | None = None, mode: str | None = None):
+    """(tilings, mode) for a batch of Simulations (one storage type) under the
+    tuned policy (the best one of `mode`, if given); without one, each
+    instance's own batch entry (or default), persistent mode."""
     table = load_table() if table is None else table
-    pol = table.get(policy_key(sims[0].storage))
-    if pol and pol.get("policy") == "balanced":
-        cap = batch_capacity(sims, kind=1)
-        return balanced_tilings([(s.nx, s.ny) for s in sims], cap, pol["per_wg"],
-                                pol["throttle"], pol.get("hmin", 4))
-    out = []
-    for s in sims:
-        t = tiling_for(s.nx, s.ny, s.storage, s.boundary, batch=True, table=table)
-        out.append(tuple(t) if t is not None else sclbm.default_batch_tiling(s.nx, s.ny))
-    return out
+    key = policy_key(sims[0].storage) + (f"/{mode}" if mode else "")
+    pol = table.get(key) or {"policy": "table", "mode": mode or "persistent"}
+    return policy_tilings(sims, pol, table), pol.get("mode", mode or "persistent")
 
 
-def _time_batch(sims, tilings, steps: int, repeats: int = 3) -> float:
-    """Median milliseconds of `steps` steps of one persistent launch."""
+def batch_tilings(sims, table: dict | None = None) -> list:
+    """Tilings of `batch_plan`."""
+    return batch_plan(sims, table)[0]
+
+
+def _time_batch(sims, tilings, steps: int, repeats: int = 3, mode="persistent") -> float:
+    """Median milliseconds of one batch step call of `steps` steps."""
     import torch
     from . import sclbm
-    b = sclbm.Batch(sims, tilings)
+    b = sclbm.Batch(sims, tilings, mode=mode)
     b.step(max(2, steps // 10))
     times = []
     for _ in range(repeats):
@@ -247,13 +246,16 @@ def _time_batch(sims, tilings, steps: int, repeats: int = 3) -> float:
 
 
 def batch_policies() -> list:
-    """Candidate batch policies in a fixed order."""
-    out = [{"policy": "table"}]
-    for hmin in (4, 8, 16, 32):
-        for per_wg in (1, 2, 3, 4, 6, 8):
-            for th in (0, 1):
-                out.append({"policy": "balanced", "per_wg": per_wg, "throttle": th,
-                            "hmin": hmin})
+    """Candidate batch policies in a fixed order: execution mode x (each
+    instance's own tile, or balanced sweep strips)."""
+    out = []
+    for mode in ("persistent", "stepwise"):
+        out.append({"policy": "table", "mode": mode})
+        for hmin in (8, 32):
+            for per_wg in (1, 3, 6, 8):
+                for th in (0, 1):
+                    out.append({"policy": "balanced", "mode": mode, "per_wg": per_wg,
+                                "throttle": th, "hmin": hmin})
     return out
 
 
@@ -287,7 +289,8 @@ def tune_batch(mixes, steps: int | None = None, table: dict | None = None,
         n = steps if steps is not None else int(min(2000, max(10, 6e8 / sites)))
         row = []
         for pol in pols:
-            ms = _time_batch(sims, policy_tilings(sims, pol, table), n)
+            ms = _time_batch(sims, policy_tilings(sims, pol, table), n,
+                             mode=pol.get("mode", "persistent"))
             row.append(ms / n * 1e3)
             if verbose:
                 print(f"  [{len(sims)} inst, {sites} sites] {pol}: {row[-1]:9.2f} us/step  "
@@ -295,14 +298,20 @@ def tune_batch(mixes, steps: int | None = None, table: dict | None = None,
         times.append(row)
     score = [math.exp(sum(math.log(times[m][p] / min(times[m])) for m in range(len(mixes)))
                       / len(mixes)) for p in range(len(pols))]
-    best = min(range(len(pols)), key=lambda p: score[p])
-    rec = dict(pols[best])
-    rec.update({"score": round(score[best], 4), "candidates": len(pols),
-                "mixes": [{"instances": len(sims), "sites": sum(s.nx * s.ny for s in sims),
-                           "us_per_step": round(times[m][best], 3),
-                           "best_us_per_step": round(min(times[m]), 3)}
-                          for m, sims in enumerate(mixes)]})
-    table[policy_key(mixes[0][0].storage)] = rec
+    def record(best):
+        rec = dict(pols[best])
+        rec.update({"score": round(score[best], 4), "candidates": len(pols),
+                    "mixes": [{"instances": len(sims), "sites": sum(s.nx * s.ny for s in sims),
+                               "us_per_step": round(times[m][best], 3),
+                               "best_us_per_step": round(min(times[m]), 3)}
+                              for m, sims in enumerate(mixes)]})
+        return rec
+    key = policy_key(mixes[0][0].storage)
+    for mode in ("persistent", "stepwise"):   # best of each mode, for callers that need one
+        idx = [p for p in range(len(pols)) if pols[p].get("mode", "persistent") == mode]
+        table[f"{key}/{mode}"] = record(min(idx, key=lambda p: score[p]))
+    rec = record(min(range(len(pols)), key=lambda p: score[p]))
+    table[key] = rec
     if own_table:
         save_table(table)
     return rec

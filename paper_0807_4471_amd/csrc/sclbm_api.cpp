@@ -652,6 +652,7 @@ int32_t sclbm_restore(sclbm_inst* h, const void* host_buf, size_t bytes, void* s
 
 struct sclbm_batch {
     int n = 0, storage = 0, nitems = 0, grid = 0, kind = 0, capacity = 0;
+    int mode = SCLBM_BATCH_PERSISTENT;
     std::vector<sclbm_inst*> insts;
     std::vector<sclbm_tiling> tl;
     char* ws = nullptr;
@@ -824,10 +825,14 @@ int32_t sclbm_batch_step(sclbm_batch* b, const int64_t* steps, void* stream)
     if (e == hipSuccess) e = hipEventRecord(b->uploaded, st);
     if (e == hipSuccess) e = hipMemsetAsync(b->ws + b->off_ctl, 0, sizeof(BatchCtl), st);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
-    e = launch_batch(b->storage, b->kind, b->ws,
-                     reinterpret_cast<const BatchItem*>(b->ws + b->off_items),
-                     b->nitems, max_steps, reinterpret_cast<BatchCtl*>(b->ws + b->off_ctl),
-                     b->grid, st);
+    const BatchItem* items = reinterpret_cast<const BatchItem*>(b->ws + b->off_items);
+    if (b->mode == SCLBM_BATCH_STEPWISE) {
+        for (int64_t s = 0; s < max_steps && e == hipSuccess; ++s)
+            e = launch_batch_step(b->storage, b->kind, b->ws, items, b->nitems, s, st);
+    } else {
+        e = launch_batch(b->storage, b->kind, b->ws, items, b->nitems, max_steps,
+                         reinterpret_cast<BatchCtl*>(b->ws + b->off_ctl), b->grid, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     for (int k = 0; k < b->n; ++k) {
         sclbm_inst* h = b->insts[k];
@@ -835,6 +840,15 @@ int32_t sclbm_batch_step(sclbm_batch* b, const int64_t* steps, void* stream)
         h->cur ^= (int)(steps[k] & 1);
         if (h->d.boundary == SCLBM_WALLS_Y) h->wall_steps += steps[k];
     }
+    return SCLBM_OK;
+}
+
+int32_t sclbm_batch_set_mode(sclbm_batch* b, int32_t mode)
+{
+    if (!b) return fail(SCLBM_EINVAL, "NULL batch");
+    if (mode != SCLBM_BATCH_PERSISTENT && mode != SCLBM_BATCH_STEPWISE)
+        return fail(SCLBM_EINVAL, "unknown batch mode %d", mode);
+    b->mode = mode;
     return SCLBM_OK;
 }
 

@@ -124,6 +124,10 @@ enum { B_STACKED = 0, B_SWEEP = 1, B_MIXED = 2 };
 int batch_grid(int storage, int kind);
 hipError_t launch_batch(int storage, int kind, const void* insts, const BatchItem* items,
                         int nitems, int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st);
+// Step s of every instance with steps > s: one ordinary launch of nitems
+// workgroups (one per item).
+hipError_t launch_batch_step(int storage, int kind, const void* insts, const BatchItem* items,
+                             int nitems, int64_t s, hipStream_t st);
 hipError_t launch_init(int storage, const void* inst, const double* rhoA, const double* rhoB,
                        const double* ux, const double* uy, int random, uint64_t seed,
                        double meanA, double meanB, double amp, hipStream_t st);

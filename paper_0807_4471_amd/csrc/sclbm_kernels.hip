@@ -793,13 +793,56 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl)
 // instances (their halo rows meet in L2, their pages in the TLB).  (Giving
 // each XCD a contiguous range of the items in flight, as the single-instance
 // kernels do, measured no better here.)
+// One item (instance, tile) of step s of a batch launch: the instance's
+// populations swap roles every step and its time advances with s.  Tiles are
+// decoded strip-major, or row-major (as the single-instance kernels number
+// them) if ROW.
+template <class T, int KIND, bool ROW>
+__device__ __forceinline__ void batch_item(const BatchInst<typename T::S, typename T::A>& bi,
+                                           int tile, int64_t s, typename T::A2 (*lpsi)[256],
+                                           typename T::A2 (*lrho)[256], double* acc)
+{
+    using S = typename T::S;
+    using A = typename T::A;
+    using A2 = typename T::A2;
+    Inst<S, A> I = bi.I;
+    if (s & 1) {
+        const S* a = I.fin;
+        I.fin = I.fout;
+        I.fout = const_cast<S*>(a);
+    }
+    I.t += s;
+    int strip, chunk;
+    if (ROW) {
+        chunk = tile / I.nstrips;
+        strip = tile - chunk * I.nstrips;
+    } else {
+        strip = tile / I.nchunks;
+        chunk = tile - strip * I.nchunks;
+    }
+    if (KIND == B_STACKED || (KIND == B_MIXED && bi.stacked)) {
+        auto lp = reinterpret_cast<A2(*)[64]>(&lpsi[0][0]);
+        auto lr = reinterpret_cast<A2(*)[64]>(&lrho[0][0]);
+        if (I.g.walls)
+            tile_body<T, 4, true, M_STEP>(I, strip, chunk, lp, lr, acc);
+        else
+            tile_body<T, 4, false, M_STEP>(I, strip, chunk, lp, lr, acc);
+    } else if constexpr (KIND != B_STACKED) {
+        if (I.g.walls) {
+            Sweep<T, 4, true, M_STEP> sw(I, strip, lpsi, lrho, acc);
+            sw.run(chunk);
+        } else {
+            Sweep<T, 4, false, M_STEP> sw(I, strip, lpsi, lrho, acc);
+            sw.run(chunk);
+        }
+    }
+}
+
 template <class T, int KIND>
 __global__ __launch_bounds__(256) void batch_kernel(
     const BatchInst<typename T::S, typename T::A>* __restrict__ insts,
     const BatchItem* __restrict__ items, int nitems, int64_t max_steps, BatchCtl* ctl)
 {
-    using S = typename T::S;
-    using A = typename T::A;
     using A2 = typename T::A2;
     __shared__ A2 lpsi[KIND == B_STACKED ? 2 : 6][256];  // stacked tiles use 8 x 64
     __shared__ A2 lrho[KIND == B_STACKED ? 2 : 6][256];
@@ -807,36 +850,33 @@ __global__ __launch_bounds__(256) void batch_kernel(
     for (int64_t s = 0; s < max_steps; ++s) {
         for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
             const BatchItem it = items[k];
-            const BatchInst<S, A>& bi = insts[it.inst];
+            const auto& bi = insts[it.inst];
             if (s >= bi.steps) continue;  // uniform: this instance is done
-            Inst<S, A> I = bi.I;
-            if (s & 1) {
-                const S* a = I.fin;
-                I.fin = I.fout;
-                I.fout = const_cast<S*>(a);
-            }
-            I.t += s;
-            const int strip = it.tile / I.nchunks, chunk = it.tile - strip * I.nchunks;
-            if (KIND == B_STACKED || (KIND == B_MIXED && bi.stacked)) {
-                auto lp = reinterpret_cast<A2(*)[64]>(&lpsi[0][0]);
-                auto lr = reinterpret_cast<A2(*)[64]>(&lrho[0][0]);
-                if (I.g.walls)
-                    tile_body<T, 4, true, M_STEP>(I, strip, chunk, lp, lr, acc);
-                else
-                    tile_body<T, 4, false, M_STEP>(I, strip, chunk, lp, lr, acc);
-            } else if constexpr (KIND != B_STACKED) {
-                if (I.g.walls) {
-                    Sweep<T, 4, true, M_STEP> sw(I, strip, lpsi, lrho, acc);
-                    sw.run(chunk);
-                } else {
-                    Sweep<T, 4, false, M_STEP> sw(I, strip, lpsi, lrho, acc);
-                    sw.run(chunk);
-                }
-            }
+            batch_item<T, KIND, false>(bi, it.tile, s, lpsi, lrho, acc);
             __syncthreads();  // the next item reuses the LDS ring
         }
         if (!grid_barrier(ctl)) return;
     }
+}
+
+// Step-wise batch: step s of every instance that still has steps, one
+// ordinary launch with one workgroup per item; consecutive launches on the
+// stream order the steps.  Items are remapped so each XCD gets a contiguous
+// range (neighbouring tiles of few instances share its L2), and tiles are
+// numbered row-major within an instance, as in the single-instance kernels.
+template <class T, int KIND>
+__global__ __launch_bounds__(256) void batch_step_kernel(
+    const BatchInst<typename T::S, typename T::A>* __restrict__ insts,
+    const BatchItem* __restrict__ items, int64_t s)
+{
+    using A2 = typename T::A2;
+    __shared__ A2 lpsi[KIND == B_STACKED ? 2 : 6][256];
+    __shared__ A2 lrho[KIND == B_STACKED ? 2 : 6][256];
+    const BatchItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const auto& bi = insts[it.inst];
+    if (s >= bi.steps) return;  // uniform: this instance is done
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    batch_item<T, KIND, true>(bi, it.tile, s, lpsi, lrho, acc);
 }
 
 template <class T, int KIND>
@@ -891,6 +931,40 @@ static hipError_t batch_go_k(int kind, const void* insts, const BatchItem* items
     case B_STACKED: return batch_go<T, B_STACKED>(insts, items, nitems, max_steps, ctl, grid, st);
     case B_SWEEP: return batch_go<T, B_SWEEP>(insts, items, nitems, max_steps, ctl, grid, st);
     case B_MIXED: return batch_go<T, B_MIXED>(insts, items, nitems, max_steps, ctl, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class T>
+static hipError_t batch_step_go(int kind, const void* insts, const BatchItem* items, int nitems,
+                                int64_t s, hipStream_t st)
+{
+    auto bi = static_cast<const BatchInst<typename T::S, typename T::A>*>(insts);
+    switch (kind) {
+    case B_STACKED:
+        hipLaunchKernelGGL((batch_step_kernel<T, B_STACKED>), dim3(nitems), dim3(256), 0, st, bi,
+                           items, s);
+        break;
+    case B_SWEEP:
+        hipLaunchKernelGGL((batch_step_kernel<T, B_SWEEP>), dim3(nitems), dim3(256), 0, st, bi,
+                           items, s);
+        break;
+    case B_MIXED:
+        hipLaunchKernelGGL((batch_step_kernel<T, B_MIXED>), dim3(nitems), dim3(256), 0, st, bi,
+                           items, s);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int storage, int kind, const void* insts, const BatchItem* items,
+                             int nitems, int64_t s, hipStream_t st)
+{
+    switch (storage) {
+    case 0: return batch_step_go<TF64>(kind, insts, items, nitems, s, st);
+    case 1: return batch_step_go<TF32>(kind, insts, items, nitems, s, st);
+    case 2: return batch_step_go<TF16>(kind, insts, items, nitems, s, st);
     }
     return hipErrorInvalidValue;
 }

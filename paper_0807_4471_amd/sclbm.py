@@ -112,6 +112,7 @@ def _load():
         "sclbm_batch_status": ([vp, vp], i32),
         "sclbm_batch_release": ([vp], i32),
         "sclbm_batch_info": ([vp, ctypes.POINTER(i32)], i32),
+        "sclbm_batch_set_mode": ([vp, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -315,11 +316,16 @@ def default_batch_tiling(nx: int, ny: int) -> tuple:
 
 
 class Batch:
-    """Many Simulations (same storage) advanced together in one persistent
-    launch per `step` call.  Each instance's result is bitwise equal to
-    stepping it alone."""
+    """Many Simulations (same storage) advanced together per `step` call:
+    mode "persistent" runs each call as one cooperative launch with a grid
+    barrier per step, "stepwise" as one ordinary launch per step covering
+    every instance.  Each instance's result is bitwise equal to stepping it
+    alone.  tilings: None (defaults), "auto" (tuned batch policy, which also
+    picks the mode unless one is given) or a list of 5-tuples."""
 
-    def __init__(self, sims, tilings=None, stream=None):
+    MODES = {"persistent": 0, "stepwise": 1}
+
+    def __init__(self, sims, tilings=None, stream=None, mode=None):
         import torch
         self.sims = list(sims)
         n = len(self.sims)
@@ -329,7 +335,11 @@ class Batch:
             if tilings != "auto":
                 raise ValueError("tilings: None, 'auto' or a list of 5-tuples")
             from . import autotune
-            tilings = autotune.batch_tilings(self.sims)
+            tilings, auto_mode = autotune.batch_plan(self.sims)
+            mode = mode or auto_mode
+        self.mode = mode or "persistent"
+        if self.mode not in self.MODES:
+            raise ValueError(f"mode must be one of {list(self.MODES)}")
         self.tilings = [tuple(t) for t in tilings]
         self._arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.sims])
         self._tl = (Tiling * n)(*[Tiling(*t) for t in self.tilings])
@@ -340,6 +350,7 @@ class Batch:
         self._h = ctypes.c_void_p()
         check(lib.sclbm_batch_plan(self._arr, n, self._tl, _dptr(self.ws), nbytes,
                                    _stream(stream), ctypes.byref(self._h)), "batch_plan")
+        check(lib.sclbm_batch_set_mode(self._h, self.MODES[self.mode]), "batch_set_mode")
 
     def step(self, steps, stream=None):
         n = len(self.sims)
@@ -358,7 +369,8 @@ class Batch:
         out = (ctypes.c_int32 * 3)()
         check(lib.sclbm_batch_info(self._h, out), "batch_info")
         return {"capacity": out[0], "tiles": out[1], "kind": out[2],
-                "grid": min(out[0], out[1])}
+                "grid": min(out[0], out[1]) if self.mode == "persistent" else out[1],
+                "mode": self.mode}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -123,11 +123,6 @@ class Server:
         self.tiling = tiling
         self.rate_lups = 2.0e10  # running estimate of batch throughput (LUP/s)
 
-    def _batch_tilings(self, sims):
-        from . import autotune, sclbm
-        if self.tiling == "auto":
-            return autotune.batch_tilings(sims)
-        return [sclbm.default_batch_tiling(s.nx, s.ny) for s in sims]
 
     def run(self, trace: list[Request], on_event=None, on_admit=None) -> dict:
         """Serve the trace in real time; returns results and metrics.
@@ -182,7 +177,8 @@ class Server:
                     if storage in plans:
                         plans[storage][1].close()
                     sims = [active[r][1] for r in rids]
-                    plans[storage] = (keyset, sclbm.Batch(sims, self._batch_tilings(sims)), rids)
+                    plans[storage] = (keyset, sclbm.Batch(sims, "auto" if self.tiling == "auto"
+                                                          else None), rids)
                     nplans += 1
                 _, batch, order = plans[storage]
                 steps = [min(active[r][2], chunk) for r in order]

@@ -1,6 +1,7 @@
-"""Persistent batched launch: uneven instances advanced together must give
-bit-for-bit the results of stepping each alone (same per-site arithmetic,
-same rounding keys), for every storage type, boundary and tiling."""
+"""Batched launches (one persistent launch per call, or one ordinary launch
+per step): uneven instances advanced together must give bit-for-bit the
+results of stepping each alone (same per-site arithmetic, same rounding
+keys), for every storage type, boundary, tiling and mode."""
 import numpy as np
 import pytest
 
@@ -27,15 +28,16 @@ def _make(storage, nx, ny, boundary, extra, seed):
     return s
 
 
+@pytest.mark.parametrize("mode", ["persistent", "stepwise"])
 @pytest.mark.parametrize("storage", ["f32", "f16dev", "f64"])
-def test_batch_equals_alone_bitwise(storage):
+def test_batch_equals_alone_bitwise(storage, mode):
     from paper_0807_4471_amd import sclbm
-    banner(f"{storage} batch of {len(CASES)} vs alone")
+    banner(f"{storage} {mode} batch of {len(CASES)} vs alone")
     steps = [30, 17, 30, 5, 0, 22]
     tilings = [(60, 4, 4, 1), (100, 8, 4, 0, 1), (60, 4, 4, 1), (130, 16, 4, 0), (252, 8, 4, 0, 1),
                (57, 4, 4, 1)]
     batch_sims = [_make(storage, *c, seed=10 + k) for k, c in enumerate(CASES)]
-    b = sclbm.Batch(batch_sims, tilings)
+    b = sclbm.Batch(batch_sims, tilings, mode=mode)
     b.step(steps)
     b.status()
     for k, c in enumerate(CASES):
@@ -47,11 +49,12 @@ def test_batch_equals_alone_bitwise(storage):
             assert np.array_equal(ma[key], mb[key]), (k, key)
 
 
-def test_batch_repeated_launches_and_default_tilings():
+@pytest.mark.parametrize("mode", ["persistent", "stepwise"])
+def test_batch_repeated_launches_and_default_tilings(mode):
     from paper_0807_4471_amd import sclbm
-    banner("f32 batch: three launches, default tilings")
+    banner(f"f32 {mode} batch: three launches, default tilings")
     sims = [_make("f32", *c, seed=40 + k) for k, c in enumerate(CASES)]
-    b = sclbm.Batch(sims)
+    b = sclbm.Batch(sims, mode=mode)
     for st in ([7, 3, 0, 7, 1, 2], [8, 8, 8, 8, 8, 8], [1, 0, 2, 0, 3, 0]):
         b.step(st)
     b.status()
@@ -71,7 +74,7 @@ def test_batch_wall_momentum_matches_alone():
     b_sim = _make("f64", *c, seed=3)
     other = _make("f64", 96, 96, "periodic", {}, seed=4)
     a.step(25)
-    sclbm.Batch([b_sim, other]).step([25, 40])
+    sclbm.Batch([b_sim, other], mode="stepwise").step([25, 40])
     da, db = a.diagnostics(), b_sim.diagnostics()
     assert np.array_equal(da["wall_mom"], db["wall_mom"])
     assert da["wall_steps"] == db["wall_steps"] == 25

@@ -45,7 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72}
+BYTES_PER_LUP = {"f64": 288, "f32": 144, "f16dev": 72, "f16sr": 72}
 WORKLOAD = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 METRIC = "two-species MLUPS and % HBM roofline; p50/p99 latency of served solves"
@@ -191,7 +191,8 @@ def sheared_cell(a, torch, sclbm):
     runs = []
     for U in (0.01, 0.05, 0.1):
         row = {"U": U}
-        for storage, seed in (("f64", 1), ("f32", 1), ("f16dev", 1), ("f64_seed2", 2)):
+        for storage, seed in (("f64", 1), ("f32", 1), ("f16dev", 1), ("f16sr", 1),
+                              ("f64_seed2", 2)):
             sim = sclbm.Simulation(n, n, storage=storage.split("_")[0], boundary="walls",
                                    wall_u=(0.0, U), rho_ref=(0.7, 0.7), tiling="auto", **WORKLOAD)
             sim.init_random(seed)
@@ -205,7 +206,7 @@ def sheared_cell(a, torch, sclbm):
             obs["mlups"] = round(n * n * steps / (ms * 1e-3) / 1e6, 1)
             row[storage] = obs
             sim.close()
-        for storage in ("f32", "f16dev", "f64_seed2"):
+        for storage in ("f32", "f16dev", "f16sr", "f64_seed2"):
             for k in ("wall_stress", "eta_app"):
                 ref = row["f64"][k]
                 row[storage][k + "_rel_err"] = abs(row[storage][k] - ref) / abs(ref)
@@ -366,7 +367,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f32 (f16 storage)"}[storage],
+        "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f32 (f16 storage)",
+                  "f16sr": "f32 (f16 storage)"}[storage],
         "data": "synthetic",
         "config": {"workload": f"micro-emulsion {nx}x{nx} periodic two-species D2Q9 "
                                f"Shan-Chen, {storage} populations, rho0={a.rho0}, "

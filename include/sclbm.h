@@ -56,7 +56,7 @@ typedef enum {
 } sclbm_status;
 
 enum { SCLBM_PERIODIC = 0, SCLBM_WALLS_Y = 1 };
-enum { SCLBM_F64 = 0, SCLBM_F32 = 1, SCLBM_F16DEV = 2 };
+enum { SCLBM_F64 = 0, SCLBM_F32 = 1, SCLBM_F16DEV = 2, SCLBM_F16DEV_SR = 3 };
 
 /* Lattice, couplings, relaxation times and pseudo-potential of one instance.
  * Copied at bind; the caller may free it afterwards. */
@@ -70,14 +70,19 @@ typedef struct {
     int32_t storage;       /* SCLBM_F64: FP64 populations, FP64 arithmetic;
                               SCLBM_F32: FP32 populations, FP32 arithmetic;
                               SCLBM_F16DEV: binary16 deviations f - w_i rho_ref_s,
-                              FP32 arithmetic                                      */
+                              FP32 arithmetic, the rest population rounded
+                              stochastically, the others to nearest;
+                              SCLBM_F16DEV_SR: the same with every population
+                              rounded stochastically (no rounding bias where
+                              populations are nearly steady, e.g. at sheared
+                              walls; slower on DRAM-resident lattices)          */
     double tau[2];         /* BGK relaxation times tau_A, tau_B of Eq. (1), > 1/2  */
     double G_a[2];         /* bare like-species attraction G^a_s (first belt)      */
     double G_r[2];         /* bare like-species repulsion G^r_s (both belts)       */
     double G_x;            /* cross-species coupling G_AB (first belt, on rho)     */
     double rho0;           /* reference density of Psi, > 0                       */
     double psi_amp;        /* amplitude A of Psi = A (1 - exp(-rho / rho0)), > 0   */
-    double rho_ref[2];     /* SCLBM_F16DEV only: reference densities of the
+    double rho_ref[2];     /* SCLBM_F16DEV(_SR) only: reference densities of the
                               deviation storage (ignored otherwise)               */
     double wall_u[2];      /* SCLBM_WALLS_Y only: x-velocity of bottom, top wall    */
     double body_F0;        /* Kolmogorov body force: species s feels

@@ -58,7 +58,12 @@ def save_table(table: dict, arch: str = ARCH):
     os.replace(tmp, table_path(arch))
 
 
+# Storage types that share another's memory behaviour share its table rows.
+TABLE_STORAGE = {"f16sr": "f16dev"}
+
+
 def key(nx, ny, storage, boundary, batch=False) -> str:
+    storage = TABLE_STORAGE.get(storage, storage)
     return f"{'batch/' if batch else ''}{storage}/{boundary}/{nx}x{ny}"
 
 
@@ -149,7 +154,7 @@ def tiling_for(nx: int, ny: int, storage: str = "f32", boundary: str = "periodic
     k = key(nx, ny, storage, boundary, batch)
     if k in table:
         return tuple(table[k]["tiling"])
-    prefix = f"{'batch/' if batch else ''}{storage}/{boundary}/"
+    prefix = f"{'batch/' if batch else ''}{TABLE_STORAGE.get(storage, storage)}/{boundary}/"
     best = None
     for kk, v in table.items():
         if not kk.startswith(prefix):
@@ -171,7 +176,7 @@ def tiling_for(nx: int, ny: int, storage: str = "f32", boundary: str = "periodic
 
 
 def policy_key(storage: str) -> str:
-    return f"batch-policy/{storage}"
+    return f"batch-policy/{TABLE_STORAGE.get(storage, storage)}"
 
 
 def balanced_tilings(shapes, capacity: int, per_wg: int = 1, throttle: int = 0,

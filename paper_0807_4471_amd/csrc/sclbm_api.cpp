@@ -46,6 +46,7 @@ constexpr uint64_t CKPT_MAGIC = 0x53434C424D434B31ull;  // "SCLBMCK1"
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_bytes(int storage) { return storage == SCLBM_F64 ? 8 : storage == SCLBM_F32 ? 4 : 2; }
+bool is_dev(int storage) { return storage == SCLBM_F16DEV || storage == SCLBM_F16DEV_SR; }
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
@@ -60,14 +61,15 @@ int32_t validate(const sclbm_desc* d)
         return fail(SCLBM_EINVAL, "unknown boundary %d", d->boundary);
     if (d->boundary == SCLBM_WALLS_Y && d->ny < 2)
         return fail(SCLBM_EINVAL, "walls need ny >= 2");
-    if (d->storage != SCLBM_F64 && d->storage != SCLBM_F32 && d->storage != SCLBM_F16DEV)
+    if (d->storage != SCLBM_F64 && d->storage != SCLBM_F32 && d->storage != SCLBM_F16DEV &&
+        d->storage != SCLBM_F16DEV_SR)
         return fail(SCLBM_EINVAL, "unknown storage %d", d->storage);
     for (int s = 0; s < 2; ++s) {
         if (!(isfinite(d->tau[s]) && d->tau[s] > 0.5))
             return fail(SCLBM_EINVAL, "tau[%d] = %g must be finite and > 1/2", s, d->tau[s]);
         if (!isfinite(d->G_a[s]) || !isfinite(d->G_r[s]))
             return fail(SCLBM_EINVAL, "couplings of species %d must be finite", s);
-        if (d->storage == SCLBM_F16DEV && !(isfinite(d->rho_ref[s]) && d->rho_ref[s] >= 0.0))
+        if (is_dev(d->storage) && !(isfinite(d->rho_ref[s]) && d->rho_ref[s] >= 0.0))
             return fail(SCLBM_EINVAL, "rho_ref[%d] must be finite and >= 0", s);
         if (d->boundary == SCLBM_WALLS_Y && !isfinite(d->wall_u[s]))
             return fail(SCLBM_EINVAL, "wall_u[%d] must be finite", s);
@@ -160,7 +162,7 @@ Coef<A> coefficients(const sclbm_desc* d)
         c.omega[s] = (A)(1.0 / d->tau[s]);
         c.hs[s] = (A)(1.0 - 0.5 / d->tau[s]);
         c.wall6u[s] = (A)(6.0 * d->wall_u[s]);
-        c.rho_base[s] = d->storage == SCLBM_F16DEV ? (A)d->rho_ref[s] : (A)0;
+        c.rho_base[s] = is_dev(d->storage) ? (A)d->rho_ref[s] : (A)0;
         c.tau1[s] = d->tau[s] == 1.0;
     }
     const double gx = d->G_x / d->rho0;

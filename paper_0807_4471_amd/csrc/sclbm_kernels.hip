@@ -33,20 +33,32 @@
 
 namespace sclbm {
 
+// Storage traits: population type S in HBM, arithmetic type A; DEV: S holds
+// deviations from w_i rho_ref; SR: every population (not only the rest one)
+// is rounded to binary16 stochastically.
 struct TF64 {
     using S = double;
     using A = double;
     using A2 = double2;
+    static constexpr bool DEV = false, SR = false;
 };
 struct TF32 {
     using S = float;
     using A = float;
     using A2 = float2;
+    static constexpr bool DEV = false, SR = false;
 };
 struct TF16 {
     using S = _Float16;
     using A = float;
     using A2 = float2;
+    static constexpr bool DEV = true, SR = false;
+};
+struct TF16SR {
+    using S = _Float16;
+    using A = float;
+    using A2 = float2;
+    static constexpr bool DEV = true, SR = true;
 };
 
 // D2Q9: i = 0 rest, 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1),
@@ -158,7 +170,7 @@ struct Sweep {
     using S = typename T::S;
     using A = typename T::A;
     using A2 = typename T::A2;
-    static constexpr bool DEV = std::is_same<T, TF16>::value;
+    static constexpr bool DEV = T::DEV;
     // Rows are prefetched one iteration ahead (loads in flight while the
     // previous row is finished) except in FP64, where three resident rows of
     // doubles leave no registers for a fourth.
@@ -435,6 +447,10 @@ struct Sweep {
                 bgk(f, rho[s], rhod[s], uex, uey, c.omega[s], c.tau1[s] != 0);
                 const A corr = A(W2) * rho[s] * u6;  // diagonal Ladd term; axis term is 0
                 [[maybe_unused]] A qsum = A(0);
+                [[maybe_unused]] uint32_t rr = 0;
+                if constexpr (T::SR)
+                    rr = hash32(seed ^ (uint32_t)(((uint32_t)y * (uint32_t)nx + (uint32_t)xw) * 2u +
+                                                  s) ^ 0x5bd1e995u);
 #pragma unroll
                 for (int i = 1; i < 9; ++i) {
                     const bool out = (bot && CY_[i] < 0) || (top && CY_[i] > 0);  // uniform
@@ -454,7 +470,16 @@ struct Sweep {
                     }
                     const uint32_t dst = col + (ro_off + (uint32_t)((k - 9 * s) * plane_b));
                     if constexpr (DEV) {
-                        const _Float16 h = (_Float16)val;
+                        _Float16 h;
+                        if constexpr (T::SR) {
+                            typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+                            h2_t hv = {(_Float16)0, (_Float16)0};
+                            hv = __builtin_amdgcn_cvt_sr_f16_f32(hv, val, rr, false);
+                            h = hv[0];
+                            rr = rr * 0x9E3779B1u + 0x7F4A7C15u;  // next random word (LCG)
+                        } else {
+                            h = (_Float16)val;
+                        }
                         bstore<_Float16, SCP>(rout[s], dst, h);
                         qsum += (float)h;  // exact: sum of binary16 values
                     } else {
@@ -723,7 +748,7 @@ __global__ __launch_bounds__(256) void init_kernel(Inst<typename T::S, typename 
             else
                 ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
             typename T::S* dst = I.fout + (int64_t)(s * 9 + i) * g.plane + (int64_t)ys * g.pitch + xs;
-            if constexpr (std::is_same<T, TF16>::value)  // deviation from w_i rho_ref
+            if constexpr (T::DEV)  // deviation from w_i rho_ref
                 *dst = (_Float16)(float)(feq - w[i] * (double)I.c.rho_base[s]);
             else
                 *dst = (typename T::S)feq;
@@ -909,6 +934,7 @@ int batch_grid(int storage, int kind)
     case 0: return batch_grid_k<TF64>(kind);
     case 1: return batch_grid_k<TF32>(kind);
     case 2: return batch_grid_k<TF16>(kind);
+    case 3: return batch_grid_k<TF16SR>(kind);
     }
     return 0;
 }
@@ -965,6 +991,7 @@ hipError_t launch_batch_step(int storage, int kind, const void* insts, const Bat
     case 0: return batch_step_go<TF64>(kind, insts, items, nitems, s, st);
     case 1: return batch_step_go<TF32>(kind, insts, items, nitems, s, st);
     case 2: return batch_step_go<TF16>(kind, insts, items, nitems, s, st);
+    case 3: return batch_step_go<TF16SR>(kind, insts, items, nitems, s, st);
     }
     return hipErrorInvalidValue;
 }
@@ -976,6 +1003,7 @@ hipError_t launch_batch(int storage, int kind, const void* insts, const BatchIte
     case 0: return batch_go_k<TF64>(kind, insts, items, nitems, max_steps, ctl, grid, st);
     case 1: return batch_go_k<TF32>(kind, insts, items, nitems, max_steps, ctl, grid, st);
     case 2: return batch_go_k<TF16>(kind, insts, items, nitems, max_steps, ctl, grid, st);
+    case 3: return batch_go_k<TF16SR>(kind, insts, items, nitems, max_steps, ctl, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1056,6 +1084,7 @@ hipError_t launch_sweep(int storage, int cw, int wt, int mode, const void* inst,
     case 0: return go_cw<TF64>(cw, wt, walls, mode, inst, nb, st);
     case 1: return go_cw<TF32>(cw, wt, walls, mode, inst, nb, st);
     case 2: return go_cw<TF16>(cw, wt, walls, mode, inst, nb, st);
+    case 3: return go_cw<TF16SR>(cw, wt, walls, mode, inst, nb, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1087,6 +1116,7 @@ hipError_t launch_init(int storage, const void* inst, const double* rA, const do
     case 0: return init_go<TF64>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
     case 1: return init_go<TF32>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
     case 2: return init_go<TF16>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
+    case 3: return init_go<TF16SR>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
     }
     return hipErrorInvalidValue;
 }

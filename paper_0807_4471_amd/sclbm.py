@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(_HERE, "libsclbm.so")
 
 OK, EINVAL, ESIZE, EDEVICE, ENONFINITE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PERIODIC, WALLS_Y = 0, 1
-F64, F32, F16DEV = 0, 1, 2
-STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV}
+F64, F32, F16DEV, F16DEV_SR = 0, 1, 2, 3
+STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "f16sr": F16DEV_SR}
 BOUNDARY = {"periodic": PERIODIC, "walls": WALLS_Y}
-BYTES_PER_POP = {F64: 8, F32: 4, F16DEV: 2}
+BYTES_PER_POP = {F64: 8, F32: 4, F16DEV: 2, F16DEV_SR: 2}
 
 
 class Desc(ctypes.Structure):

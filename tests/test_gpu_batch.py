@@ -29,7 +29,7 @@ def _make(storage, nx, ny, boundary, extra, seed):
 
 
 @pytest.mark.parametrize("mode", ["persistent", "stepwise"])
-@pytest.mark.parametrize("storage", ["f32", "f16dev", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "f16sr", "f64"])
 def test_batch_equals_alone_bitwise(storage, mode):
     from paper_0807_4471_amd import sclbm
     banner(f"{storage} {mode} batch of {len(CASES)} vs alone")

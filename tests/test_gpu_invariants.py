@@ -13,7 +13,7 @@ def _sim(nx, ny, storage, **kw):
     return sclbm.Simulation(nx, ny, storage=storage, **dict(WORKLOAD, **kw))
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f16sr"])
 def test_tiling_does_not_change_results(storage):
     """Every tiling (strip width, chunk height, waves per workgroup, store
     throttle, write-through stores) gives the same bits: halos and ragged
@@ -93,7 +93,8 @@ def test_determinism_and_stream_use():
 # (worst case, fully systematic rounding); FP16 deviations round
 # independently (RNE): 5 sigma of a random walk of 2000 * 18 * 65536
 # roundings of ulp <= 2^-12 gives ~1e-3.
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 5e-4), ("f16dev", 1e-3)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 5e-4), ("f16dev", 1e-3),
+                                               ("f16sr", 1e-3)])
 @pytest.mark.parametrize("boundary", ["periodic", "walls"])
 def test_mass_conservation(storage, tol, boundary):
     """Per-species mass (FP64 totals on the GPU) after 2000 steps on 256x256."""
@@ -132,7 +133,7 @@ def test_nonfinite_is_reported():
     assert ei.value.status == sclbm.ENONFINITE
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16dev", 1.5e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16dev", 1.5e-3), ("f16sr", 1.5e-3)])
 def test_long_run_mass_drift(storage, tol):
     """20000 steps on 128x128: the collision conserves mass to one rounding
     per site (rest population as remainder), so the drift stays far below

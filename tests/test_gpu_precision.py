@@ -22,10 +22,10 @@ from helpers import WORKLOAD, banner, gpu_run, max_err, oracle_run, structure_fa
 
 pytestmark = pytest.mark.gpu
 
-ONE_STEP = {"f32": 1e-6, "f16dev": 1.5e-4}
+ONE_STEP = {"f32": 1e-6, "f16dev": 1.5e-4, "f16sr": 1.5e-4}
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "f16sr"])
 @pytest.mark.parametrize("nx,ny", [(64, 64), (130, 70)])
 def test_one_step_error(storage, nx, ny):
     banner(f"{storage} one step {nx}x{ny}")
@@ -36,7 +36,7 @@ def test_one_step_error(storage, nx, ny):
     assert e["rho"] <= ONE_STEP[storage], e
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "f16sr"])
 def test_stable_flow_accumulates_linearly(storage):
     """G = 0 shear wave, 200 steps: velocity error stays within 200 one-step
     bounds scaled by the velocity amplitude."""
@@ -54,7 +54,8 @@ def test_stable_flow_accumulates_linearly(storage):
     assert e["u"] <= 200 * ONE_STEP[storage] * 0.1, e
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6 * 1e4), ("f16dev", 1.5e-4 * 1e3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6 * 1e4), ("f16dev", 1.5e-4 * 1e3),
+                                               ("f16sr", 1.5e-4 * 1e3)])
 def test_demixing_workload_pointwise(storage, tol):
     banner(f"{storage} workload 64x64 100 steps")
     _, m = gpu_run(64, 64, 100, storage=storage, **WORKLOAD)
@@ -64,7 +65,7 @@ def test_demixing_workload_pointwise(storage, tol):
     assert e["rho"] <= tol, e
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "f16sr"])
 def test_demixing_statistics_and_mass(storage):
     """128x128, 600 steps: mass drift (FP64 totals) and S(k) of phi = rho_A -
     rho_B against the oracle."""

@@ -20,8 +20,12 @@ NX, NY, STEPS, LAST = 128, 64, 2000, 500
 # initial state grows by orders of magnitude within 1000 steps), which the
 # arithmetic alone does not bound: the tolerances are 3x the largest error
 # measured over U in {0.01, 0.05, 0.1} (FP32 5.0e-4 / 4.5e-3, FP16
-# deviations 3.2e-2 / 2.2e-2).
-TOL = {"f64": (1e-9, 1e-9), "f32": (1.5e-3, 1.5e-2), "f16dev": (0.1, 0.07)}
+# deviations 3.2e-2 / 2.2e-2, FP16 with stochastic rounding of every
+# population 5.5e-2 / -).  The latter's apparent viscosity from one final
+# snapshot is dominated by its rounding noise at the lowest shear (measured
+# relative error 1.1 at U = 0.01): it is reported, not asserted.
+TOL = {"f64": (1e-9, 1e-9), "f32": (1.5e-3, 1.5e-2), "f16dev": (0.1, 0.07),
+       "f16sr": (0.17, None)}
 
 
 def oracle_observables(U, seed):
@@ -57,7 +61,7 @@ def gpu_observables(U, seed, storage):
 _ref_cache = {}
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f16sr"])
 @pytest.mark.parametrize("U", [0.01, 0.05, 0.1])
 def test_shear_observables_against_oracle(U, storage):
     banner(f"sheared cell {NX}x{NY} U={U} {storage} {STEPS} steps")
@@ -71,4 +75,6 @@ def test_shear_observables_against_oracle(U, storage):
           f"eta {got['eta_app']:.9e} vs {eta_ref:.9e} (rel {e_eta:.2e})", flush=True)
     assert got["wall_steps"] == LAST and got["bad_sites"] == 0
     tol_s, tol_eta = TOL[storage]
-    assert e_s <= tol_s and e_eta <= tol_eta
+    assert e_s <= tol_s
+    if tol_eta is not None:
+        assert e_eta <= tol_eta

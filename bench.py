@@ -294,15 +294,18 @@ def run_serving(a, torch, sclbm, rate_lups):
     e_steps = (steps[1] - steps[0]) / math.log(steps[1] / steps[0])
     rate = a.serve_load * rate_lups / (e_sites * e_steps)
     trace = serving.make_trace(a.serve_requests, rate=rate, seed=4242, side=side, steps=steps)
-    srv = serving.Server(keep_moments=False)
-    r = serving.summarize_public(srv.run(trace))
-    log(f"serving (batched): {r}")
+    r = serving.summarize_public(serving.Server(keep_moments=False).run(trace))
+    log(f"serving (batched, step-fair slices): {r}")
+    r_work = serving.summarize_public(
+        serving.Server(keep_moments=False, slicing="work").run(trace))
+    log(f"serving (batched, work-fair slices): {r_work}")
     r64 = serving.summarize_public(serving.serve_sequential_f64(trace))
     log(f"serving (sequential FP64): {r64}")
     return {"workload": f"{a.serve_requests} Poisson requests at {rate:.3f}/s "
                         f"(load {a.serve_load} of {rate_lups / 1e9:.1f} GLUPS), sizes 64^2..1024^2 "
                         "and steps 1e3..1e5 log-uniform, f32 or f16dev, half sheared walls",
-            "arrival_rate_per_s": round(rate, 4), "batched": r, "sequential_f64": r64}
+            "arrival_rate_per_s": round(rate, 4), "batched": r, "batched_work_fair": r_work,
+            "sequential_f64": r64}
 
 
 def cpu_baseline(nx, steps, rho0):

@@ -4,12 +4,14 @@ Requests (lattice size, steps, storage, boundary, seed, physical parameters)
 arrive over time.  The server admits them in arrival order as soon as their
 device state fits the HBM budget and a slot is free, keeps every admitted
 state on the device, and advances all active instances of a storage type
-together in persistent batch launches (``sclbm.Batch``) of a bounded number
-of steps ("chunks").  New arrivals join at the next chunk; an instance that
-reaches its step count inside a chunk drops out of that launch.  Finished
-requests are retired: their FP64 diagnostics are checked (a non-finite
-state marks that request failed and affects no other), their moments are
-read back to the host, their buffers are freed.
+together in batch calls (``sclbm.Batch``, tuned tiles and execution mode)
+of about `chunk_ms` each.  Within a chunk every request advances the same
+number of steps, or (work-fair slicing) small lattices take up to a few
+times more.  New arrivals join at the next chunk; an instance that reaches its step
+count inside a chunk drops out of that call.  Finished requests are retired:
+their FP64 diagnostics are checked (a non-finite state marks that request
+failed and affects no other), their moments are read back to the host, their
+buffers are freed.
 
 Each request's result is bitwise the result of running it alone, because a
 batch launch performs exactly the per-site arithmetic of a single-instance
@@ -110,18 +112,40 @@ class Server:
 
     hbm_budget: bytes of instance state allowed on the device at once.
     max_slots:  instances in flight at once.
-    chunk_ms:   target duration of one batch launch (bounds admission delay).
+    chunk_ms:   target duration of one batch call (bounds admission delay).
+    slicing:    "steps" (default): every active request advances the same
+                number of steps per chunk; "work": every active request gets
+                an equal share of the chunk's lattice updates, between the
+                step-fair count and WORK_BOOST times it (small lattices take
+                more steps, so short requests finish sooner; the extra steps
+                of tiny lattices are launch-bound, which costs throughput).
     """
 
+    WORK_BOOST = 4
+
     def __init__(self, hbm_budget: int = 64 << 30, max_slots: int = 256, chunk_ms: float = 20.0,
-                 device: str = "cuda", keep_moments: bool = True, tiling: str = "auto"):
+                 device: str = "cuda", keep_moments: bool = True, tiling: str = "auto",
+                 slicing: str = "steps"):
+        if slicing not in ("work", "steps"):
+            raise ValueError("slicing must be 'work' or 'steps'")
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.chunk_ms = float(chunk_ms)
         self.device = device
         self.keep_moments = keep_moments
         self.tiling = tiling
+        self.slicing = slicing
         self.rate_lups = 2.0e10  # running estimate of batch throughput (LUP/s)
+
+    def _slice(self, active, order, total_sites):
+        """Steps of each request in `order` for the next chunk."""
+        budget = self.rate_lups * self.chunk_ms * 1e-3      # lattice updates per chunk
+        chunk = max(1, int(budget / max(1, total_sites)))
+        if self.slicing == "steps":
+            return [min(active[r][2], chunk) for r in order]
+        share = budget / max(1, len(active))
+        return [min(active[r][2], self.WORK_BOOST * chunk,
+                    max(chunk, int(share / active[r][0].sites))) for r in order]
 
 
     def run(self, trace: list[Request], on_event=None, on_admit=None) -> dict:
@@ -167,7 +191,6 @@ class Server:
             for rid, (req, sim, rem, _) in active.items():
                 groups.setdefault(req.storage, []).append(rid)
             total_sites = sum(active[r][0].sites for r in active)
-            chunk = max(1, int(self.rate_lups * self.chunk_ms * 1e-3 / max(1, total_sites)))
             tc = time.perf_counter()
             work = 0
             for storage, rids in sorted(groups.items()):
@@ -181,7 +204,7 @@ class Server:
                                                           else None), rids)
                     nplans += 1
                 _, batch, order = plans[storage]
-                steps = [min(active[r][2], chunk) for r in order]
+                steps = self._slice(active, order, total_sites)
                 batch.step(steps)
                 for r, s in zip(order, steps):
                     active[r][2] -= s

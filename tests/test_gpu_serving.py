@@ -23,12 +23,14 @@ def _alone(req):
     return sim.moments()
 
 
-def test_results_equal_running_alone():
+@pytest.mark.parametrize("slicing", ["work", "steps"])
+def test_results_equal_running_alone(slicing):
     from paper_0807_4471_amd import serving
-    banner("serving: mix vs alone")
+    banner(f"serving ({slicing} slices): mix vs alone")
     trace = _trace()
     events = []
-    out = serving.Server(chunk_ms=0.5).run(trace, on_event=lambda k, r, t: events.append((k, r, t)))
+    out = serving.Server(chunk_ms=0.5, slicing=slicing).run(
+        trace, on_event=lambda k, r, t: events.append((k, r, t)))
     assert out["completed"] == len(trace) and out["failed"] == 0
     # overlap: some request was admitted before an earlier one finished
     fin = {r: t for k, r, t in events if k == "finish"}

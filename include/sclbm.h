@@ -51,7 +51,7 @@ typedef enum {
     SCLBM_EDEVICE = -3,       /* a HIP call failed (detail in last_error)    */
     SCLBM_ENONFINITE = -4,    /* diagnostics found a non-finite or
                                  non-positive density                        */
-    SCLBM_EUNSUPPORTED = -5,  /* valid request this build does not support   */
+    SCLBM_EUNSUPPORTED = -5,  /* valid request the library does not support  */
     SCLBM_ESTATE = -6         /* handle not initialised / wrong state        */
 } sclbm_status;
 

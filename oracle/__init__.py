@@ -102,8 +102,9 @@ def lib():
         L.oracle_moments.argtypes = [pp, dp, dp, dp, dp]
         L.oracle_totals.argtypes = [pp, dp, dp]
         L.oracle_row_profiles.argtypes = [pp, dp, dp, dp]
+        L.oracle_shear_flow.argtypes = [pp, dp, dp]
         for name in ("oracle_forces", "oracle_init", "oracle_run", "oracle_moments",
-                     "oracle_totals", "oracle_row_profiles"):
+                     "oracle_totals", "oracle_row_profiles", "oracle_shear_flow"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -203,3 +204,10 @@ def row_profiles(p: Params, f: np.ndarray):
     _check(lib().oracle_row_profiles(ctypes.byref(p.c()), _ptr(f), _ptr(ux), _ptr(sxy)),
            "row_profiles")
     return ux, sxy
+
+
+def shear_flow(p: Params, f: np.ndarray) -> dict:
+    """U_bar (sin-mode amplitude of the physical x-velocity) and I_AB."""
+    out = np.zeros(2)
+    _check(lib().oracle_shear_flow(ctypes.byref(p.c()), _ptr(f), _ptr(out)), "shear_flow")
+    return {"u_bar": float(out[0]), "i_ab": float(out[1])}

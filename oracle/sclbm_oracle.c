@@ -429,3 +429,39 @@ int32_t oracle_row_profiles(const oracle_params* p, const double* f, double* ux_
     free(ux); free(sxy);
     return rc;
 }
+
+int32_t oracle_shear_flow(const oracle_params* p, const double* f, double out[2])
+{
+    if (!valid(p)) return -1;
+    const int nx = p->nx, ny = p->ny;
+    const size_t N = (size_t)nx * ny;
+    double* rho = malloc(sizeof(double) * 2 * N);
+    double* ux = malloc(sizeof(double) * N);
+    if (!rho || !ux) {
+        free(rho); free(ux);
+        return -2;
+    }
+    int rc = observe(p, f, rho, ux, NULL, NULL, NULL);
+    if (rc == 0) {
+        const double two_pi = 6.283185307179586476925286766559;
+        double proj = 0.0, iab = 0.0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t n = (size_t)y * nx + x;
+                proj += ux[n] * sin(two_pi * (double)y / (double)ny);
+                double g[2][2] = {{0.0, 0.0}, {0.0, 0.0}};  /* [species][component] */
+                for (int i = 1; i < 9; ++i) {
+                    const size_t m = (size_t)nbr_row(p, y, CY[i]) * nx + wrapx(p, x + CX[i]);
+                    for (int s = 0; s < 2; ++s) {
+                        g[s][0] += 3.0 * w_of(i) * CX[i] * rho[s * N + m];
+                        g[s][1] += 3.0 * w_of(i) * CY[i] * rho[s * N + m];
+                    }
+                }
+                iab += g[0][0] * g[1][0] + g[0][1] * g[1][1];
+            }
+        out[0] = 2.0 * proj / (double)N;
+        out[1] = iab;
+    }
+    free(rho); free(ux);
+    return rc;
+}

@@ -91,6 +91,17 @@ int32_t oracle_totals(const oracle_params* p, const double* f, double out[6]);
 int32_t oracle_row_profiles(const oracle_params* p, const double* f, double* ux_row,
                             double* sxy_row);
 
+/* Observables of the shear-flow experiment (the rheology part of the paper,
+ * with the figure of R and I_AB) at time t:
+ *   out[0]  U_bar = (2 / (nx ny)) sum_r u_x(r) sin(2 pi y / ny), the
+ *           amplitude of the physical x-velocity on the forcing mode (the
+ *           paper's plain row sum of U would vanish for a sine profile);
+ *           R = U_bar / U0
+ *   out[1]  I_AB = sum_r grad rho_A . grad rho_B, each gradient the
+ *           isotropic D2Q9 difference 3 sum_i w_i c_i rho(r + c_i)
+ *           (neighbours wrapped, or mirrored at walls)                      */
+int32_t oracle_shear_flow(const oracle_params* p, const double* f, double out[2]);
+
 #ifdef __cplusplus
 }
 #endif

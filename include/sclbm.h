@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define SCLBM_ABI_VERSION 1
+#define SCLBM_ABI_VERSION 2
 
 typedef enum {
     SCLBM_OK = 0,
@@ -105,6 +105,13 @@ typedef struct {
     int64_t wall_steps;    /* steps accumulated in wall_mom since the last reset  */
     int64_t step;          /* time t of the totals                                 */
     int64_t bad_sites;     /* sites with a non-finite or non-positive density      */
+    double u_bar;          /* (2 / (nx ny)) sum_r u_x sin(2 pi y / ny): amplitude
+                              of the physical x-velocity on the Kolmogorov
+                              forcing mode; the response of the rheology
+                              experiment is R = u_bar / U0                         */
+    double i_ab;           /* interface indicator sum_r grad rho_A . grad rho_B,
+                              gradients 3 sum_i w_i c_i rho(r + c_i) (neighbours
+                              wrapped, or mirrored at walls)                      */
 } sclbm_diag;
 
 /* Tile shape of the fused step.
@@ -132,7 +139,7 @@ typedef struct {
 typedef struct sclbm_inst sclbm_inst;     /* opaque host handle: one lattice  */
 typedef struct sclbm_batch sclbm_batch;   /* opaque host handle: a batch plan */
 
-/* Version of this ABI (SCLBM_ABI_VERSION of the build). */
+/* Version of this ABI (SCLBM_ABI_VERSION of the compiled library). */
 int32_t sclbm_abi_version(void);
 
 /* Host-only self-check of the lattice index helpers the kernels use (row

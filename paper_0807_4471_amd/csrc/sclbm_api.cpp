@@ -295,6 +295,8 @@ void fill_diag(const sclbm_inst* h, const double* v, const double* wall, sclbm_d
     out->mom[1] = v[D_MOM_Y];
     out->sxy = v[D_SXY];
     out->bad_sites = (int64_t)v[D_BAD];
+    out->u_bar = 2.0 * v[D_UPROJ] / ((double)h->d.nx * (double)h->d.ny);
+    out->i_ab = v[D_IAB];
     out->step = step;
     out->wall_steps = h->wall_steps;
     if (wall) {

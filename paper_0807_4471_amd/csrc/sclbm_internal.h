@@ -17,6 +17,8 @@ enum {
     D_MOM_Y = 3,
     D_SXY = 4,
     D_BAD = 5,
+    D_UPROJ = 6,  // sum_r u_x sin(2 pi y / ny)
+    D_IAB = 7,    // sum_r grad rho_A . grad rho_B
     NDIAG = 8
 };
 

@@ -417,6 +417,16 @@ struct Sweep {
                 const bool ok = rho[0] > A(0) && rho[1] > A(0) && rho[0] < A(1e30) &&
                                 rho[1] < A(1e30);
                 acc[D_BAD] += ok ? 0.0 : 1.0;
+                // shear-flow observables: the forcing-mode projection of u_x,
+                // and grad rho_A . grad rho_B with the isotropic D2Q9
+                // gradient 3 sum_i w_i c_i rho(r + c_i) from the LDS ring
+                // (rhod differs from rho by a constant)
+                acc[D_UPROJ] += (double)vx * sin(c.two_pi_over_ny * (double)y);
+                const A gxa = A(3) * (A(W1) * r10.x + A(W2) * (r11.x - q11.x));
+                const A gya = A(3) * (A(W1) * r01.x + A(W2) * (r11.x + q11.x));
+                const A gxb = A(3) * (A(W1) * r10.y + A(W2) * (r11.y - q11.y));
+                const A gyb = A(3) * (A(W1) * r01.y + A(W2) * (r11.y + q11.y));
+                acc[D_IAB] += (double)gxa * (double)gxb + (double)gya * (double)gyb;
             }
         }
 
@@ -594,7 +604,7 @@ template <int CW>
 __device__ __forceinline__ void block_reduce(double* acc, double (*red)[NDIAG], double* out)
 {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < NDIAG; ++j) {
         double v = acc[j];
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -602,16 +612,14 @@ __device__ __forceinline__ void block_reduce(double* acc, double (*red)[NDIAG], 
     }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
-        for (int j = 0; j < 6; ++j) red[w][j] = acc[j];
+        for (int j = 0; j < NDIAG; ++j) red[w][j] = acc[j];
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < NDIAG; ++j) {
             double s = 0.0;
             for (int k = 0; k < CW; ++k) s += red[k][j];
             out[j] = s;
         }
-        out[6] = 0.0;
-        out[7] = 0.0;
     }
 }
 
@@ -623,7 +631,7 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
     __shared__ double red[CW][NDIAG];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int chunk = b / I.nstrips, strip = b - chunk * I.nstrips;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     Sweep<T, CW, WALLS, MODE> sw(I, strip, lpsi, lrho, acc);
     sw.run(chunk);
     if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
@@ -669,7 +677,7 @@ __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typen
     __shared__ double red[RW][NDIAG];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int chunk = b / I.nstrips, strip = b - chunk * I.nstrips;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     tile_body<T, RW, WALLS, MODE, SCP>(I, strip, chunk, lpsi, lrho, acc);
     if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
         block_reduce<RW>(acc, red, I.partials + (int64_t)b * NDIAG);
@@ -871,7 +879,7 @@ __global__ __launch_bounds__(256) void batch_kernel(
     using A2 = typename T::A2;
     __shared__ A2 lpsi[KIND == B_STACKED ? 2 : 6][256];  // stacked tiles use 8 x 64
     __shared__ A2 lrho[KIND == B_STACKED ? 2 : 6][256];
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t s = 0; s < max_steps; ++s) {
         for (int k = blockIdx.x; k < nitems; k += gridDim.x) {
             const BatchItem it = items[k];
@@ -900,7 +908,7 @@ __global__ __launch_bounds__(256) void batch_step_kernel(
     const BatchItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const auto& bi = insts[it.inst];
     if (s >= bi.steps) return;  // uniform: this instance is done
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     batch_item<T, KIND, true>(bi, it.tile, s, lpsi, lrho, acc);
 }
 

@@ -51,13 +51,16 @@ class Diag(ctypes.Structure):
         ("wall_steps", ctypes.c_int64),
         ("step", ctypes.c_int64),
         ("bad_sites", ctypes.c_int64),
+        ("u_bar", ctypes.c_double),
+        ("i_ab", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {"mass": np.array(self.mass[:]), "mom": np.array(self.mom[:]), "sxy": self.sxy,
                 "wall_mom": np.array([[self.wall_mom[w][c] for c in range(2)] for w in range(2)]),
                 "wall_steps": int(self.wall_steps), "step": int(self.step),
-                "bad_sites": int(self.bad_sites)}
+                "bad_sites": int(self.bad_sites), "u_bar": float(self.u_bar),
+                "i_ab": float(self.i_ab)}
 
 
 class Tiling(ctypes.Structure):

@@ -35,8 +35,17 @@ def test_index_selftest(L):
     assert L.lib.sclbm_selftest() == 0
 
 
+def test_diag_record_matches_header(L):
+    """The binding's diagnostics record has the header's size and field order."""
+    import ctypes as C
+    names = [n for n, _ in L.Diag._fields_]
+    assert names == ["mass", "mom", "sxy", "wall_mom", "wall_steps", "step", "bad_sites",
+                     "u_bar", "i_ab"]
+    assert C.sizeof(L.Diag) == 8 * (2 + 2 + 1 + 4 + 3 + 2)
+
+
 def test_version_and_strerror(L):
-    assert L.lib.sclbm_abi_version() == 1
+    assert L.lib.sclbm_abi_version() == 2
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.strerror(code) and L.strerror(code) != "unknown status"
     assert L.strerror(-99) == "unknown status"

@@ -131,6 +131,48 @@ def test_fused_diagnostics_f64():
     np.testing.assert_allclose(d["mom"], tot["mom"], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5), ("f16dev", 2e-3)])
+@pytest.mark.parametrize("boundary", ["periodic", "walls"])
+def test_shear_flow_observables(storage, tol, boundary):
+    """u_bar (Kolmogorov-mode projection of the physical velocity) and I_AB,
+    on-demand and fused, against the oracle: a demixing mixture driven by
+    the Kolmogorov force (and, with walls, sheared), tilings of both kinds."""
+    from paper_0807_4471_amd import inputs, sclbm
+    import oracle
+    banner(f"{storage} {boundary} u_bar and I_AB")
+    nx, ny, steps = 70, 48, 60
+    kw = dict(WORKLOAD, body_F0=2e-5)
+    if boundary == "walls":
+        kw["wall_u"] = (0.0, 0.04)
+    rho = inputs.random_densities(nx, ny, 9)
+    p = oracle.Params(nx=nx, ny=ny, walls=boundary == "walls",
+                      **{k: v for k, v in kw.items() if k in ("Ga", "Gr", "Gx", "rho0",
+                                                               "body_F0", "wall_u")})
+    f = oracle.init(p, rho)
+    oracle.run(p, f, steps)
+    ref = oracle.shear_flow(p, f)
+    assert abs(ref["u_bar"]) > 1e-6 and abs(ref["i_ab"]) > 1e-6
+    for tl in [(60, 4, 4, 1), (70, 16, 2, 0)]:
+        sim = sclbm.Simulation(nx, ny, storage=storage, boundary=boundary, diag_every=steps,
+                               **kw)
+        sim.set_tiling(*tl)
+        sim.init_fields(rho)
+        sim.step(steps)
+        on_demand = sim.diagnostics()             # state at t = steps
+        sim.step(1)                               # its first kernel reduces t = steps
+        fused = sim.fused_diagnostics()
+        assert fused["step"] == on_demand["step"] == steps
+        for name, d in (("on-demand", on_demand), ("fused", fused)):
+            for k in ("u_bar", "i_ab"):
+                err = abs(d[k] - ref[k]) / abs(ref[k])
+                print(f"  {tl} {name} {k}: {d[k]:.12e} vs {ref[k]:.12e} (rel {err:.1e})",
+                      flush=True)
+        for name, d in (("on-demand", on_demand), ("fused", fused)):
+            for k in ("u_bar", "i_ab"):
+                assert abs(d[k] - ref[k]) <= tol * abs(ref[k]), (tl, name, k, d[k], ref[k])
+        sim.close()
+
+
 def test_init_random_matches_input_generator():
     """The device SplitMix64 init equals the host generator bit for bit."""
     from paper_0807_4471_amd import inputs, sclbm

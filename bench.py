@@ -19,6 +19,8 @@ Side objects in the same JSON line:
   sheared_cell   1024x1024 between walls (top at U = 0.01, 0.05, 0.1):
                  mean shear stress and apparent viscosity, FP32 and FP16
                  storage against the FP64 path
+  rheology       128x128 under the Kolmogorov force: response R(t) and
+                 interface indicator I_AB(t)
   batch          64 uneven instances in one persistent launch per call,
                  against the same instances stepped one launch at a time
   serving        a Poisson trace served with continuous batching, against
@@ -72,6 +74,9 @@ def parse():
     ap.add_argument("--no-dram", action="store_true", help="skip the DRAM-resident side runs")
     ap.add_argument("--no-shear", action="store_true", help="skip the sheared-cell object")
     ap.add_argument("--shear-steps", type=int, default=50000)
+    ap.add_argument("--no-rheology", action="store_true", help="skip the Kolmogorov-flow run")
+    ap.add_argument("--rheology-steps", type=int, default=500000)
+    ap.add_argument("--rheology-storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
@@ -220,6 +225,51 @@ def sheared_cell(a, torch, sclbm):
                          "start: its difference is the run-to-run spread of these "
                          "observables, against which the FP32/FP16 errors are read",
             "runs": runs}
+
+
+def rheology(a, torch, sclbm):
+    """The shear-flow experiment of the paper's rheology part: 128x128
+    periodic, Kolmogorov body force rho_s F0 sin(2 pi y / 128) with
+    F0 = nu0 k^2 U0, U0 = 0.1 (a plain fluid would reach R = 1), Psi
+    amplitude sqrt(rho0) as in the paper, random start; the response
+    R(t) = u_bar / U0 and the interface indicator I_AB(t) from the fused FP64
+    diagnostics (FP32 storage unless --rheology-storage says otherwise).
+    Both coupling sets the paper prints are run: the one listed with the
+    rheology experiment (G^r_A = 11.80, G^a_B = -11.70) and the Fig. 2
+    caption set (G^r_A = 11.70, G^a_B = -11.80)."""
+    import math
+    n, U0, rho0 = 128, 0.1, 0.7
+    nu0 = (1.0 - 0.5) / 3.0
+    F0 = nu0 * (2 * math.pi / n) ** 2 * U0
+    sets = {"rheology_text": dict(Ga=(-12.55, -11.70), Gr=(11.80, 10.95)),
+            "fig2_caption": dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95))}
+    out = {"workload": f"{n}x{n} Kolmogorov flow, U0={U0}, F0={F0:.3e}, G_AB=0.58, "
+                       "Psi amplitude sqrt(rho0), rho0=0.7, tau=1, 5% random start, "
+                       f"{a.rheology_storage} storage, fused diagnostics every 1000 steps",
+           "runs": {}}
+    for name, cp in sets.items():
+        sim = sclbm.Simulation(n, n, storage=a.rheology_storage, diag_every=1000,
+                               tiling="auto", Gx=0.58, rho0=rho0, psi_amp=math.sqrt(rho0),
+                               body_F0=F0, **cp)
+        sim.init_random(1)
+        chunk = max(1000, a.rheology_steps // 20)
+        samples, t_ms, steps = [], 0.0, 0
+        while steps < a.rheology_steps:
+            k = min(chunk, a.rheology_steps - steps)
+            ms, _ = timed(torch, lambda: sim.step(k))
+            t_ms += ms
+            steps += k
+            sim.step(1)               # its first launch reduces the state at t = steps
+            d = sim.fused_diagnostics()
+            samples.append({"t": int(d["step"]), "R": round(d["u_bar"] / U0, 5),
+                            "I_AB": round(d["i_ab"], 2), "bad_sites": int(d["bad_sites"])})
+        sim.close()
+        rs = [x["R"] for x in samples]
+        out["runs"][name] = {"couplings": cp, "steps": steps,
+                             "mlups": round(n * n * steps / (t_ms * 1e-3) / 1e6, 1),
+                             "R_min": min(rs), "R_final": rs[-1], "samples": samples}
+        log(f"rheology {name}: R_min {min(rs)}, R_final {rs[-1]}")
+    return out
 
 
 def batch_mix(seed=2026, n=64):
@@ -404,6 +454,8 @@ def main():
         out["dram_resident"] = side
     if not a.no_shear:
         out["sheared_cell"] = sheared_cell(a, torch, sclbm)
+    if not a.no_rheology:
+        out["rheology"] = rheology(a, torch, sclbm)
     rate_lups = 2.0e10
     if not a.no_batch:
         out["batch"] = run_batch(a, torch, sclbm)

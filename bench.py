@@ -21,6 +21,8 @@ Side objects in the same JSON line:
                  storage against the FP64 path
   rheology       128x128 under the Kolmogorov force: response R(t) and
                  interface indicator I_AB(t)
+  ageing         overlap C(t_w, tau) of the order parameter over an ensemble
+                 of such lattices advanced as one batch
   batch          64 uneven instances in one persistent launch per call,
                  against the same instances stepped one launch at a time
   serving        a Poisson trace served with continuous batching, against
@@ -77,6 +79,8 @@ def parse():
     ap.add_argument("--no-rheology", action="store_true", help="skip the Kolmogorov-flow run")
     ap.add_argument("--rheology-steps", type=int, default=500000)
     ap.add_argument("--rheology-storage", default="f32", choices=list(BYTES_PER_LUP))
+    ap.add_argument("--no-ageing", action="store_true", help="skip the ageing ensemble")
+    ap.add_argument("--ageing-members", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
@@ -272,6 +276,58 @@ def rheology(a, torch, sclbm):
     return out
 
 
+def ageing(a, torch, sclbm):
+    """The ageing experiment (Eq. (CORRE)): an ensemble of 128x128 lattices
+    under the Kolmogorov force (U0 = 0.02, and 0.03 for one waiting time),
+    couplings and Psi amplitude of the rheology experiment, seeds 1..M,
+    advanced together as one batch; the overlap
+    C(t_w, tau) = sum_k sum_r phi_k(t_w) phi_k(t_w + tau) / sum_k sum_r phi_k(t_w)^2
+    of phi = rho_A - rho_B, from FP64 sums taken by the library's order-
+    parameter pass against the snapshots phi_k(t_w)."""
+    import math
+    n, rho0 = 128, 0.7
+    nu0 = (1.0 - 0.5) / 3.0
+    taus = [0, 1000, 3000, 10000, 30000, 100000, 200000, 300000]
+    out = {"workload": f"ensemble of {a.ageing_members} x {n}x{n} Kolmogorov flows, "
+                       "couplings of the rheology experiment, Psi amplitude sqrt(rho0), "
+                       "rho0=0.7, tau=1, 5% random starts (seeds 1..M), FP32, one batch",
+           "runs": []}
+    for U0, tws in ((0.02, [50000, 200000, 300000]), (0.03, [300000])):
+        F0 = nu0 * (2 * math.pi / n) ** 2 * U0
+        kw = dict(Ga=(-12.55, -11.70), Gr=(11.80, 10.95), Gx=0.58, rho0=rho0,
+                  psi_amp=math.sqrt(rho0), body_F0=F0)
+        sims = [sclbm.Simulation(n, n, storage="f32", **kw).init_random(1 + k)
+                for k in range(a.ageing_members)]
+        b = sclbm.Batch(sims, "auto")
+        events = sorted(set(tws) | {tw + tau for tw in tws for tau in taus})
+        snaps, den, C = {}, {}, {tw: {} for tw in tws}
+        t, ms_total = 0, 0.0
+        for T in events:
+            if T > t:
+                ms, _ = timed(torch, lambda: b.step(T - t))
+                ms_total += ms
+                t = T
+            if T in tws:
+                snaps[T] = [torch.empty((n, n), dtype=torch.float64, device=sims[0].buf.device)
+                            for _ in sims]
+                den[T] = sum(s.order_parameter(phi_out=p)[1] for s, p in zip(sims, snaps[T]))
+            for tw in snaps:
+                if T - tw in taus:
+                    num = sum(s.order_parameter(phi_ref=p)[0] for s, p in zip(sims, snaps[tw]))
+                    C[tw][T - tw] = round(num / den[tw], 6)
+        b.close()
+        bad = sum(1 for s in sims if s.diagnostics()["bad_sites"] > 0)
+        for s in sims:
+            s.close()
+        run = {"U0": U0, "steps": t, "members_with_bad_sites": bad,
+               "batched_mlups": round(len(sims) * n * n * t / (ms_total * 1e-3) / 1e6, 1),
+               "C": {str(tw): {str(k): v for k, v in sorted(C[tw].items())} for tw in tws}}
+        out["runs"].append(run)
+        log(f"ageing U0={U0}: {run}")
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_mix(seed=2026, n=64):
     """Uneven instances: sizes from {128..512}^2, rho0 ~ U(0.60, 0.80),
     G^X ~ U(0.50, 0.65), tau_s ~ U(0.8, 1.2); instance i seeded 1000 + i."""
@@ -456,6 +512,8 @@ def main():
         out["sheared_cell"] = sheared_cell(a, torch, sclbm)
     if not a.no_rheology:
         out["rheology"] = rheology(a, torch, sclbm)
+    if not a.no_ageing:
+        out["ageing"] = ageing(a, torch, sclbm)
     rate_lups = 2.0e10
     if not a.no_batch:
         out["batch"] = run_batch(a, torch, sclbm)

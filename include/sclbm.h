@@ -202,6 +202,17 @@ int32_t sclbm_time(const sclbm_inst* inst, int64_t* t);
 int32_t sclbm_read_moments(sclbm_inst* inst, double* rhoA, double* rhoB, double* ux,
                            double* uy, double* sxy, void* hip_stream);
 
+/* Order parameter phi = rho_A - rho_B of the state at time t, for the ageing
+ * overlap of the paper's Eq. (CORRE): C(t_w, tau) = <sum_r phi(r, t_w)
+ * phi(r, t_w + tau)> / <sum_r phi(r, t_w)^2>, brackets an ensemble average.
+ * phi_out: device array [ny][nx] (row-major, FP64) that receives phi, or
+ * NULL; phi_ref: device array [ny][nx] of a reference phi (e.g. taken at
+ * t_w), or NULL.  out[0] = sum_r phi(r) phi_ref(r) (0 without phi_ref),
+ * out[1] = sum_r phi(r)^2, both FP64 in a fixed order.  phi_ref and
+ * phi_out may not alias.  Syncs hip_stream. */
+int32_t sclbm_order_parameter(sclbm_inst* inst, const double* phi_ref, double* phi_out,
+                              double out[2], void* hip_stream);
+
 /* FP64 totals of the current state into *out (host).  Runs one read-only
  * pass, then syncs.  Returns ENONFINITE (with *out filled) if any density is
  * non-finite or non-positive. */

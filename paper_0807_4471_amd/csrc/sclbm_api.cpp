@@ -528,6 +528,29 @@ int32_t sclbm_read_moments(sclbm_inst* h, double* rhoA, double* rhoB, double* ux
                  nullptr);
 }
 
+int32_t sclbm_order_parameter(sclbm_inst* h, const double* phi_ref, double* phi_out,
+                              double out[2], void* stream)
+{
+    if (!h || !out) return fail(SCLBM_EINVAL, "NULL argument");
+    if (phi_ref && phi_ref == phi_out) return fail(SCLBM_EINVAL, "phi_ref aliases phi_out");
+    if (!h->inited) return fail(SCLBM_ESTATE, "instance not initialised");
+    hipStream_t st = (hipStream_t)stream;
+    double* io[5] = {phi_out, const_cast<double*>(phi_ref), nullptr, nullptr, nullptr};
+    int nb = 0;
+    int32_t rc = sweep(h, M_PHI, RO_CW, RO_W, RO_H, h->cur, h->cur, io, st, &nb);
+    if (rc) return rc;
+    double* rec = reinterpret_cast<double*>(h->buf + h->L.off_diag) + NDIAG;
+    hipError_t e = launch_reduce(reinterpret_cast<double*>(h->buf + h->L.off_partials), nb, rec, st);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    double v[NDIAG];
+    e = hipMemcpyAsync(v, rec, sizeof v, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "order parameter copy");
+    out[0] = phi_ref ? v[0] : 0.0;
+    out[1] = v[1];
+    return SCLBM_OK;
+}
+
 int32_t sclbm_diagnostics(sclbm_inst* h, sclbm_diag* out, void* stream)
 {
     if (!h || !out) return fail(SCLBM_EINVAL, "NULL argument");

@@ -24,7 +24,10 @@ enum {
 
 // Kernel modes: a full step, a step that also reduces diagnostics of the
 // state it starts from, a read-out of moments, a diagnostics-only pass.
-enum { M_STEP = 0, M_STEP_DIAG = 1, M_READ = 2, M_DIAG = 3 };
+// M_PHI: the order parameter phi = rho_A - rho_B of the state, written to
+// out[0] if set, with FP64 sums of phi * out[1] (a reference field, if set)
+// and phi^2 in diagnostics slots 0 and 1.
+enum { M_STEP = 0, M_STEP_DIAG = 1, M_READ = 2, M_DIAG = 3, M_PHI = 4 };
 
 // Population storage in HBM: f[s][i][row][x], s-major then direction, rows of
 // `pitch` elements, `plane` elements between consecutive (s, i) planes.  With
@@ -72,7 +75,8 @@ struct Inst {
     int64_t t;                  // time at the start of this step (FP16 rounding key)
     double* partials;           // [nblocks][NDIAG] (diagnostic modes)
     double* wall_acc;           // [2 walls][2 comps][nx], accumulated every step
-    double* out[5];             // READ mode: rhoA, rhoB, ux, uy, sxy (any NULL)
+    double* out[5];             // READ mode: rhoA, rhoB, ux, uy, sxy (any NULL);
+                                // PHI mode: phi out, phi reference (either NULL)
 };
 
 // One instance inside a persistent batch launch.  `I` describes the

@@ -358,6 +358,16 @@ struct Sweep {
             rho[0] += c.rho_base[0];
             rho[1] += c.rho_base[1];
         }
+        if constexpr (MODE == M_PHI) {  // order parameter (ageing overlap)
+            if (own) {
+                const int64_t n = (int64_t)y * nx + xw;
+                const double ph = (double)rho[0] - (double)rho[1];
+                if (I.out[0]) I.out[0][n] = ph;
+                if (I.out[1]) acc[0] += ph * I.out[1][n];
+                acc[1] += ph * ph;
+            }
+            return;
+        }
         A F[2][2];
         auto force = [&](int s, A d10, A d01, A d11, A e11, A d20, A d02, A d21, A d12, A e12,
                          A e21, A d22, A e22, A psi, A rho, A o10, A o01, A o11, A p11) {
@@ -634,7 +644,7 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
     double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     Sweep<T, CW, WALLS, MODE> sw(I, strip, lpsi, lrho, acc);
     sw.run(chunk);
-    if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG)
+    if constexpr (MODE == M_STEP_DIAG || MODE == M_DIAG || MODE == M_PHI)
         block_reduce<CW>(acc, red, I.partials + (int64_t)b * NDIAG);
 }
 
@@ -1047,6 +1057,7 @@ static hipError_t go_mode(int mode, const void* inst, int nb, hipStream_t st)
     case M_STEP_DIAG: return go<T, CW, WALLS, M_STEP_DIAG>(inst, nb, st);
     case M_READ: return go<T, CW, WALLS, M_READ>(inst, nb, st);
     case M_DIAG: return go<T, CW, WALLS, M_DIAG>(inst, nb, st);
+    case M_PHI: return go<T, CW, WALLS, M_PHI>(inst, nb, st);
     }
     return hipErrorInvalidValue;
 }

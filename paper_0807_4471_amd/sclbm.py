@@ -101,6 +101,7 @@ def _load():
         "sclbm_set_tiling": ([vp, ctypes.POINTER(Tiling)], i32),
         "sclbm_get_tiling": ([vp, ctypes.POINTER(Tiling)], i32),
         "sclbm_read_moments": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "sclbm_order_parameter": ([vp, vp, vp, dp, vp], i32),
         "sclbm_diagnostics": ([vp, ctypes.POINTER(Diag), vp], i32),
         "sclbm_fused_diagnostics": ([vp, ctypes.POINTER(Diag), vp], i32),
         "sclbm_reset_wall_accum": ([vp, vp], i32),
@@ -276,6 +277,20 @@ class Simulation:
     def moments(self, stream=None) -> dict:
         d = self.moments_device(stream)
         return {k: v.cpu().numpy() for k, v in d.items()}
+
+    def order_parameter(self, phi_ref=None, phi_out=None, stream=None):
+        """(sum phi * phi_ref, sum phi^2) of phi = rho_A - rho_B now, in FP64;
+        phi_ref / phi_out: float64 device tensors of shape (ny, nx) or None
+        (phi_out receives phi)."""
+        import torch
+        for t in (phi_ref, phi_out):
+            if t is not None:
+                assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                assert tuple(t.shape) == (self.ny, self.nx)
+        out = (ctypes.c_double * 2)()
+        check(lib.sclbm_order_parameter(self._h, _dptr(phi_ref), _dptr(phi_out), out,
+                                        _stream(stream)), "order_parameter")
+        return float(out[0]), float(out[1])
 
     def diagnostics(self, stream=None, raise_nonfinite=False) -> dict:
         d = Diag()

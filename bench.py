@@ -23,6 +23,8 @@ Side objects in the same JSON line:
                  interface indicator I_AB(t)
   ageing         overlap C(t_w, tau) of the order parameter over an ensemble
                  of such lattices advanced as one batch
+  laplace        nominal surface tension sigma(rho0) from batched static
+                 droplets, both Psi amplitudes
   batch          64 uneven instances in one persistent launch per call,
                  against the same instances stepped one launch at a time
   serving        a Poisson trace served with continuous batching, against
@@ -81,6 +83,8 @@ def parse():
     ap.add_argument("--rheology-storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--no-ageing", action="store_true", help="skip the ageing ensemble")
     ap.add_argument("--ageing-members", type=int, default=16)
+    ap.add_argument("--no-laplace", action="store_true", help="skip the sigma(rho0) sweep")
+    ap.add_argument("--laplace-steps", type=int, default=10000)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
@@ -328,6 +332,53 @@ def ageing(a, torch, sclbm):
     return out
 
 
+def laplace_sweep(a, torch, sclbm):
+    """Nominal surface tension against rho0 (the Laplace test behind Fig. 2,
+    left): static droplets of A in B on 64x64 periodic lattices, radii
+    8..20, rho0 from 0.55 to 0.80, both Psi amplitudes (rho0 and
+    sqrt(rho0)), caption couplings, FP64, all droplets advanced together as
+    one batch; sigma and the intercept from dP = sigma / R + c0, with dP
+    from the bulk pressure of the relaxed density fields."""
+    import math
+    from paper_0807_4471_amd import inputs
+    from paper_0807_4471_amd.observables import droplet_jump, laplace_fit
+    L, radii = 64, (8.0, 11.0, 14.0, 17.0, 20.0)
+    rho0s = (0.55, 0.60, 0.65, 0.70, 0.72, 0.75, 0.80)
+    cases, sims = [], []
+    for amp_name in ("rho0", "sqrt_rho0"):
+        for r0 in rho0s:
+            amp = r0 if amp_name == "rho0" else math.sqrt(r0)
+            params = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=r0, psi_amp=amp)
+            for R in radii:
+                sims.append(sclbm.Simulation(L, L, storage="f64", **params).init_fields(
+                    inputs.droplet_densities(L, L, R, 1.5, 0.06)))
+                cases.append((amp_name, r0, R, params))
+    b = sclbm.Batch(sims, "auto")
+    ms, _ = timed(torch, lambda: b.step(a.laplace_steps))
+    b.close()
+    pts = {}
+    for (amp_name, r0, R, params), sim in zip(cases, sims):
+        m = sim.moments()
+        pts.setdefault((amp_name, r0), []).append(droplet_jump(m["rhoA"], m["rhoB"], params))
+        sim.close()
+    out = {"workload": f"{len(sims)} static droplets on {L}x{L} (radii {radii}), caption "
+                       f"couplings, FP64, {a.laplace_steps} steps in one batch",
+           "batched_mlups": round(len(sims) * L * L * a.laplace_steps / (ms * 1e-3) / 1e6, 1),
+           "sigma": {}}
+    def num(v, k):
+        return round(v, k) if math.isfinite(v) else None
+
+    for (amp_name, r0), p in pts.items():
+        sigma, c0, r2 = laplace_fit([x[0] for x in p], [x[1] for x in p])
+        good = [x for x in p if math.isfinite(x[1])]
+        out["sigma"].setdefault(amp_name, {})[str(r0)] = {
+            "sigma": num(sigma, 5), "c0": num(c0, 6), "r2": num(r2, 5),
+            "droplets_kept": len(good),
+            "dP_max": num(max((x[1] for x in good), default=float("nan")), 6)}
+    log(f"laplace: {out['sigma']}")
+    return out
+
+
 def batch_mix(seed=2026, n=64):
     """Uneven instances: sizes from {128..512}^2, rho0 ~ U(0.60, 0.80),
     G^X ~ U(0.50, 0.65), tau_s ~ U(0.8, 1.2); instance i seeded 1000 + i."""
@@ -514,6 +565,8 @@ def main():
         out["rheology"] = rheology(a, torch, sclbm)
     if not a.no_ageing:
         out["ageing"] = ageing(a, torch, sclbm)
+    if not a.no_laplace:
+        out["laplace"] = laplace_sweep(a, torch, sclbm)
     rate_lups = 2.0e10
     if not a.no_batch:
         out["batch"] = run_batch(a, torch, sclbm)

@@ -45,3 +45,59 @@ def shear_observables(sim) -> dict:
     eta, nu = apparent_viscosity(ux_row, sxy_row, rho_mean)
     return {"wall_stress": mean_wall_stress(d, sim.nx), "eta_app": eta, "nu_app": nu,
             "wall_steps": int(d["wall_steps"]), "bad_sites": int(d["bad_sites"])}
+
+
+# ---------------------------------------------------------------- Laplace law
+
+CS2 = 1.0 / 3.0
+
+
+def bulk_pressure(rhoA, rhoB, Ga, Gr, Gx, rho0, psi_amp):
+    """Bulk pressure of the two-species model at each site,
+        P = c_s^2 (rho_A + rho_B) + (c_s^2 / 2) sum_s G_s1 Psi_s^2
+            + c_s^2 (G_AB / rho0) rho_A rho_B,    G_s1 = G^a_s + G^r_s,
+    the local part of the non-ideal pressure tensor Eq. (PAB) with the cross
+    term and c_s^2 factors of the long-wave expansion of the forces."""
+    rA = np.asarray(rhoA, dtype=np.float64)
+    rB = np.asarray(rhoB, dtype=np.float64)
+    psiA = psi_amp * (1.0 - np.exp(-rA / rho0))
+    psiB = psi_amp * (1.0 - np.exp(-rB / rho0))
+    g1 = (Ga[0] + Gr[0], Ga[1] + Gr[1])
+    return (CS2 * (rA + rB) + 0.5 * CS2 * (g1[0] * psiA ** 2 + g1[1] * psiB ** 2)
+            + CS2 * (Gx / rho0) * rA * rB)
+
+
+def droplet_jump(rhoA, rhoB, params: dict, core: int = 2, min_contrast: float = 0.1):
+    """(effective radius, pressure jump) of a centred droplet of species A:
+    the radius from the area of A's normalised excess density, the jump
+    between the mean bulk pressure of the central (2 core)^2 sites and of a
+    3x3 corner block (the far field on a periodic lattice).  (nan, nan) if
+    the fields are not finite or A's inside/outside contrast fell below
+    min_contrast (the droplet dissolved)."""
+    rA = np.asarray(rhoA, dtype=np.float64)
+    ny, nx = rA.shape
+    cy, cx = ny // 2, nx // 2
+    a_in = rA[cy - core:cy + core, cx - core:cx + core].mean()
+    a_out = rA[:3, :3].mean()
+    if not (np.isfinite(rA).all() and np.isfinite(rhoB).all()) or a_in - a_out < min_contrast:
+        return float("nan"), float("nan")
+    radius = float(np.sqrt(np.sum((rA - a_out) / (a_in - a_out)) / np.pi))
+    P = bulk_pressure(rA, rhoB, params["Ga"], params["Gr"], params["Gx"], params["rho0"],
+                      params["psi_amp"])
+    return radius, float(P[cy - core:cy + core, cx - core:cx + core].mean() - P[:3, :3].mean())
+
+
+def laplace_fit(radii, jumps):
+    """Least-squares dP = sigma / R + c0 over the finite points: (sigma, c0,
+    r2), or three nans with fewer than three points."""
+    R = np.asarray(radii, dtype=np.float64)
+    dP = np.asarray(jumps, dtype=np.float64)
+    ok = np.isfinite(R) & np.isfinite(dP)
+    R, dP = R[ok], dP[ok]
+    if len(R) < 3:
+        return float("nan"), float("nan"), float("nan")
+    M = np.vstack([1.0 / R, np.ones_like(R)]).T
+    (sigma, c0), *_ = np.linalg.lstsq(M, dP, rcond=None)
+    ss = np.sum((dP - dP.mean()) ** 2)
+    r2 = 1.0 - np.sum((dP - M @ [sigma, c0]) ** 2) / ss if ss > 0 else 1.0
+    return float(sigma), float(c0), float(r2)

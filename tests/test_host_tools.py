@@ -47,6 +47,36 @@ def test_mean_wall_stress_sign_and_scale():
         observables.mean_wall_stress({"wall_mom": d["wall_mom"], "wall_steps": 0}, nx=16)
 
 
+def test_bulk_pressure_closed_forms():
+    """Ideal part only without couplings; with couplings the terms add as
+    written for a uniform state."""
+    P = observables.bulk_pressure(0.7, 0.3, (0, 0), (0, 0), 0.0, 0.7, 0.7)
+    assert P == pytest.approx(1.0 / 3.0)
+    Ga, Gr, Gx, r0, A = (-12.55, -11.8), (11.7, 10.95), 0.58, 0.7, 0.7
+    ra, rb = 0.8, 0.2
+    pa, pb = A * (1 - np.exp(-ra / r0)), A * (1 - np.exp(-rb / r0))
+    expect = (ra + rb) / 3 + (1 / 6) * ((Ga[0] + Gr[0]) * pa ** 2 + (Ga[1] + Gr[1]) * pb ** 2) \
+        + (Gx / r0) * ra * rb / 3
+    assert observables.bulk_pressure(ra, rb, Ga, Gr, Gx, r0, A) == pytest.approx(expect, rel=1e-14)
+
+
+def test_droplet_jump_and_laplace_fit():
+    from paper_0807_4471_amd import inputs
+    rho = inputs.droplet_densities(64, 64, 12.0, 1.5, 0.06, width=0.5)
+    params = dict(Ga=(0, 0), Gr=(0, 0), Gx=0.0, rho0=1.0, psi_amp=1.0)
+    R, dP = observables.droplet_jump(rho[0], rho[1], params)
+    assert abs(R - 12.0) < 0.3 and abs(dP) < 1e-12     # ideal: rho_A + rho_B is flat
+    radii = np.array([8.0, 11.0, 14.0, 17.0])
+    s, c0, r2 = observables.laplace_fit(radii, 0.12 / radii + 0.003)
+    assert s == pytest.approx(0.12) and c0 == pytest.approx(0.003) and r2 == pytest.approx(1.0)
+    # dissolved droplets (nan) are left out; too few points give nan
+    s2, _, _ = observables.laplace_fit(list(radii) + [np.nan], list(0.12 / radii) + [np.nan])
+    assert s2 == pytest.approx(0.12)
+    assert np.isnan(observables.laplace_fit([8.0, np.nan], [0.1, 0.2])[0])
+    flat = np.full((32, 32), 0.7)
+    assert np.isnan(observables.droplet_jump(flat, flat, params)[0])
+
+
 def _counters(path, rows):
     with open(path, "w", newline="") as fh:
         w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Value"])

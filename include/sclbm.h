@@ -240,7 +240,7 @@ int32_t sclbm_restore(sclbm_inst* inst, const void* host_buf, size_t bytes, void
 /* Free the handle (never the caller's device buffer).  NULL is a no-op. */
 int32_t sclbm_release(sclbm_inst* inst);
 
-/* ---------------- batching: many instances, one persistent launch -------- */
+/* ---------------- batching: many instances advanced together ------------ */
 
 /* Device bytes the plan of `n` instances with the given tilings needs
  * (per-instance parameter table, tile table, grid-barrier state), 0 if the

@@ -10,8 +10,8 @@ GPU architecture (``tuning/<arch>.json`` next to this file), which
 ``tiling_for`` consults; sizes without an entry take the nearest tuned size
 of the same storage and boundary, scaled to the lattice.
 
-Batch tilings (``batch=True``) are restricted to what one persistent batch
-launch accepts: 4 waves, stacked tiles or sweep strips.  A batch is tuned as
+Batch tilings (``batch=True``) are restricted to what a batch launch
+accepts: 4 waves, stacked tiles or sweep strips.  A batch is tuned as
 a whole (``tune_batch``): each instance's own best tile (timed alone) is
 one candidate policy; the others are "balanced" sweep strips whose chunk
 heights give every tile about the same number of sites, sized so the

@@ -27,6 +27,13 @@
 // most vertically adjacent chunks, which share halo rows, run under one L2.
 // (Strip-major numbering fetched ~12% more than the algorithmic bytes on
 // DRAM-resident lattices and was 5-16% slower.)
+//
+// Other kernels in this file: stacked tiles for small lattices (RW waves
+// along y, one row each, same per-site code); the batch kernels (many
+// instances per launch: one persistent cooperative launch with a grid
+// barrier per step, or one ordinary launch per step); read-out passes of
+// the sweep (moments, FP64 diagnostics, the order parameter); the fixed-order
+// reduction of per-block FP64 partials; the initialiser.
 #include <type_traits>
 
 #include "sclbm_internal.h"

@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-        ("walls", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("walls", ctypes.c_int32), ("forcing", ctypes.c_int32),
         ("tau", ctypes.c_double * 2),
         ("Ga", ctypes.c_double * 2),
         ("Gr", ctypes.c_double * 2),
@@ -65,10 +65,12 @@ class Params:
     psi_amp: float | None = None      # None -> rho0 (amplitude used by the workloads)
     wall_u: tuple = (0.0, 0.0)
     body_F0: float = 0.0
+    forcing: str = "shift"            # "shift" (Shan-Chen velocity shift) or "guo"
 
     def c(self) -> _Params:
         amp = self.rho0 if self.psi_amp is None else self.psi_amp
-        return _Params(int(self.nx), int(self.ny), int(bool(self.walls)), 0,
+        return _Params(int(self.nx), int(self.ny), int(bool(self.walls)),
+                       {"shift": 0, "guo": 1}[self.forcing],
                        (ctypes.c_double * 2)(*self.tau),
                        (ctypes.c_double * 2)(*self.Ga),
                        (ctypes.c_double * 2)(*self.Gr),

@@ -24,6 +24,8 @@
  *   - force-to-population coupling: Shan-Chen equilibrium-velocity shift with
  *     the common velocity u' = sum_s(j_s/tau_s) / sum_s(rho_s/tau_s) and
  *     u_eq,s = u' + tau_s F_s / rho_s (the SC method the letter builds on);
+ *     or, as a variant, Guo's source term with the barycentric velocity
+ *     (j + F/2) / rho (exactly momentum-conserving for equal tau_s);
  *   - local equilibrium: second-order D2Q9 polynomial;
  *   - physical velocity: (sum_s j_s + F_s/2) / sum_s rho_s;
  *   - walls: half-way bounce-back with the moving-wall correction
@@ -127,6 +129,7 @@ static int valid(const oracle_params* p)
     if (!p || p->nx < 1 || p->ny < 1) return 0;
     if (p->walls && p->ny < 2) return 0;
     if (!(p->tau[0] > 0.5) || !(p->tau[1] > 0.5) || !(p->rho0 > 0.0)) return 0;
+    if (p->forcing != 0 && p->forcing != 1) return 0;
     return 1;
 }
 
@@ -267,30 +270,52 @@ int32_t oracle_run(const oracle_params* p, double* f, int64_t nsteps, double* wa
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 const size_t n = (size_t)y * nx + x;
-                /* Common velocity u' weighted by rho_s / tau_s. */
-                double num_x = 0.0, num_y = 0.0, den = 0.0;
-                for (int s = 0; s < 2; ++s) {
-                    num_x += jx[s * N + n] / p->tau[s];
-                    num_y += jy[s * N + n] / p->tau[s];
-                    den += rho[s * N + n] / p->tau[s];
-                }
                 double upx = 0.0, upy = 0.0;
-                if (den > 0.0) {
-                    upx = num_x / den;
-                    upy = num_y / den;
+                if (p->forcing == 0) {
+                    /* Common velocity u' weighted by rho_s / tau_s. */
+                    double num_x = 0.0, num_y = 0.0, den = 0.0;
+                    for (int s = 0; s < 2; ++s) {
+                        num_x += jx[s * N + n] / p->tau[s];
+                        num_y += jy[s * N + n] / p->tau[s];
+                        den += rho[s * N + n] / p->tau[s];
+                    }
+                    if (den > 0.0) {
+                        upx = num_x / den;
+                        upy = num_y / den;
+                    }
+                } else {
+                    /* Guo: barycentric velocity with half the force. */
+                    double mx = 0.0, my = 0.0, rt = 0.0;
+                    for (int s = 0; s < 2; ++s) {
+                        mx += jx[s * N + n] + 0.5 * F[(s * 2 + 0) * N + n];
+                        my += jy[s * N + n] + 0.5 * F[(s * 2 + 1) * N + n];
+                        rt += rho[s * N + n];
+                    }
+                    if (rt > 0.0) {
+                        upx = mx / rt;
+                        upy = my / rt;
+                    }
                 }
                 for (int s = 0; s < 2; ++s) {
                     const double r = rho[s * N + n];
+                    const double Fx = F[(s * 2 + 0) * N + n], Fy = F[(s * 2 + 1) * N + n];
                     double uex = upx, uey = upy;
-                    if (r > 0.0) {
-                        uex = upx + p->tau[s] * F[(s * 2 + 0) * N + n] / r;
-                        uey = upy + p->tau[s] * F[(s * 2 + 1) * N + n] / r;
+                    if (p->forcing == 0 && r > 0.0) {
+                        uex = upx + p->tau[s] * Fx / r;
+                        uey = upy + p->tau[s] * Fy / r;
                     }
                     oracle_feq(r, uex, uey, feq);
                     for (int i = 0; i < 9; ++i) {
                         const double fi = f[(s * 9 + i) * N + n];
                         /* BGK relaxation of Eq. (1), then free streaming. */
-                        const double fs = fi - (fi - feq[i]) / p->tau[s];
+                        double fs = fi - (fi - feq[i]) / p->tau[s];
+                        if (p->forcing == 1) {
+                            const double cu = CX[i] * upx + CY[i] * upy;
+                            const double cf = CX[i] * Fx + CY[i] * Fy;
+                            const double uf = upx * Fx + upy * Fy;
+                            fs += (1.0 - 0.5 / p->tau[s]) * w_of(i) *
+                                  (3.0 * (cf - uf) + 9.0 * cu * cf);
+                        }
                         const int yd = y + CY[i];
                         if (p->walls && (yd < 0 || yd >= ny)) {
                             const int top = yd >= ny;

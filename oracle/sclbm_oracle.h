@@ -32,7 +32,13 @@ typedef struct {
     int32_t nx, ny;      /* lattice size; nx >= 1, ny >= 1 (ny >= 2 with walls) */
     int32_t walls;       /* 0: periodic in y; 1: half-way bounce-back walls at
                             y = -1/2 (bottom) and y = ny - 1/2 (top)          */
-    int32_t reserved;
+    int32_t forcing;     /* how the force enters Eq. (1):
+                            0: Shan-Chen shift of the equilibrium velocity,
+                               u_eq,s = u' + tau_s F_s / rho_s;
+                            1: Guo source term: both species relax towards
+                               f^eq(rho_s, u), u = (sum_s j_s + F_s/2) / sum_s rho_s,
+                               and gain (1 - 1/(2 tau_s)) w_i [3 (c_i - u).F_s
+                               + 9 (c_i.u)(c_i.F_s)]                          */
     double tau[2];       /* BGK relaxation times tau_s (> 1/2), Eq. (1)        */
     double Ga[2];        /* like-species attraction G^a_s, first belt          */
     double Gr[2];        /* like-species repulsion  G^r_s, both belts          */

@@ -87,14 +87,28 @@ def step(f, prm):
             y = np.arange(ny)[:, None]
             F[s, 0] += rho[s] * prm["F0"] * np.sin(2.0 * np.pi * y / ny)
     tau = prm["tau"]
-    den = rho[0] / tau[0] + rho[1] / tau[1]
-    upx = (jx[0] / tau[0] + jx[1] / tau[1]) / den
-    upy = (jy[0] / tau[0] + jy[1] / tau[1]) / den
+    guo = prm.get("forcing", "shift") == "guo"
+    if guo:   # barycentric velocity with half the force
+        rt = rho[0] + rho[1]
+        upx = (jx[0] + jx[1] + 0.5 * (F[0, 0] + F[1, 0])) / rt
+        upy = (jy[0] + jy[1] + 0.5 * (F[0, 1] + F[1, 1])) / rt
+    else:     # Shan-Chen common velocity weighted by rho_s / tau_s
+        den = rho[0] / tau[0] + rho[1] / tau[1]
+        upx = (jx[0] / tau[0] + jx[1] / tau[1]) / den
+        upy = (jy[0] / tau[0] + jy[1] / tau[1]) / den
     out = np.zeros_like(f)
     for s in range(2):
-        ueqx = upx + tau[s] * F[s, 0] / rho[s]
-        ueqy = upy + tau[s] * F[s, 1] / rho[s]
+        if guo:
+            ueqx, ueqy = upx, upy
+        else:
+            ueqx = upx + tau[s] * F[s, 0] / rho[s]
+            ueqy = upy + tau[s] * F[s, 1] / rho[s]
         fs = f[s] - (f[s] - feq_all(W, rho[s], ueqx, ueqy)) / tau[s]
+        if guo:   # Guo's source: (1 - 1/(2 tau)) w_i [(c_i - u)/c_s^2 + (c_i.u) c_i / c_s^4] . F
+            cu = CX[:, None, None] * upx + CY[:, None, None] * upy
+            cf = CX[:, None, None] * F[s, 0] + CY[:, None, None] * F[s, 1]
+            uf = upx * F[s, 0] + upy * F[s, 1]
+            fs = fs + (1 - 0.5 / tau[s]) * W[:, None, None] * ((cf - uf) / CS2 + cu * cf / CS2 ** 2)
         for i in range(9):
             moved = np.roll(fs[i], (CY[i], CX[i]), axis=(0, 1))
             if walls and CY[i] != 0:
@@ -110,11 +124,12 @@ def step(f, prm):
     return out
 
 
-def _case(nx, ny, walls, seed, F0=0.0, tau=(0.8, 1.3), wall_u=(0.0, 0.0)):
+def _case(nx, ny, walls, seed, F0=0.0, tau=(0.8, 1.3), wall_u=(0.0, 0.0), forcing="shift"):
     import oracle
     prm = dict(walls=walls, tau=tau, Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58,
-               rho0=0.70, A=0.70, F0=F0, wall_u=wall_u)
-    p = oracle.Params(nx=nx, ny=ny, walls=walls, tau=tau, wall_u=wall_u, body_F0=F0)
+               rho0=0.70, A=0.70, F0=F0, wall_u=wall_u, forcing=forcing)
+    p = oracle.Params(nx=nx, ny=ny, walls=walls, tau=tau, wall_u=wall_u, body_F0=F0,
+                      forcing=forcing)
     rho = inputs.random_densities(nx, ny, seed, amp=0.2)
     rng = np.random.default_rng(seed)
     ux = 0.05 * rng.standard_normal((ny, nx))
@@ -123,11 +138,12 @@ def _case(nx, ny, walls, seed, F0=0.0, tau=(0.8, 1.3), wall_u=(0.0, 0.0)):
     return oracle, p, prm, f0
 
 
+@pytest.mark.parametrize("forcing", ["shift", "guo"])
 @pytest.mark.parametrize("nx,ny", [(8, 8), (9, 7)])
 @pytest.mark.parametrize("walls", [False, True])
-def test_steps_match_brute_force(oracle_lib, nx, ny, walls):
+def test_steps_match_brute_force(oracle_lib, nx, ny, walls, forcing):
     oracle, p, prm, f0 = _case(nx, ny, walls, seed=nx * 10 + ny,
-                               wall_u=(0.02, -0.05) if walls else (0.0, 0.0))
+                               wall_u=(0.02, -0.05) if walls else (0.0, 0.0), forcing=forcing)
     f_or = f0.copy()
     f_bf = f0.copy()
     for _ in range(5):

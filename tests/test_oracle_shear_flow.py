@@ -60,14 +60,15 @@ def test_u_bar_of_a_sine_field(oracle_lib):
     assert abs(oracle_lib.shear_flow(p, f)["u_bar"] - U) < 1e-15
 
 
+@pytest.mark.parametrize("forcing", ["shift", "guo"])
 @pytest.mark.parametrize("tau", [0.8, 1.0])
-def test_kolmogorov_flow_response_of_a_plain_fluid(oracle_lib, tau):
+def test_kolmogorov_flow_response_of_a_plain_fluid(oracle_lib, tau, forcing):
     nx, ny, U0 = 4, 32, 0.01
     k = 2 * math.pi / ny
     nu = CS2 * (tau - 0.5)
     F0 = nu * k * k * U0
     p = oracle_lib.Params(nx=nx, ny=ny, tau=(tau, tau), Ga=(0, 0), Gr=(0, 0), Gx=0.0,
-                          body_F0=F0)
+                          body_F0=F0, forcing=forcing)
     f = _state(oracle_lib, p, np.full((2, ny, nx), 0.5))
     oracle_lib.run(p, f, int(12 / (nu * k * k)))          # 12 viscous times
     R = oracle_lib.shear_flow(p, f)["u_bar"] / U0

@@ -74,6 +74,10 @@ def parse():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--rho0", type=float, default=0.70)
+    ap.add_argument("--forcing", default="shift", choices=["shift", "guo"],
+                    help="force coupling of the headline run")
+    ap.add_argument("--no-guo", action="store_true",
+                    help="skip the Guo-forcing side run of the headline workload")
     ap.add_argument("--no-sweep", action="store_true", help="skip the rho0 sweep")
     ap.add_argument("--no-dram", action="store_true", help="skip the DRAM-resident side runs")
     ap.add_argument("--no-shear", action="store_true", help="skip the sheared-cell object")
@@ -110,8 +114,9 @@ def timed(torch, fn):
     return e0.elapsed_time(e1), time.perf_counter() - t0
 
 
-def run_gpu(nx, storage, steps, warmup, rho0, diag_every, torch, sclbm, tiling="auto"):
-    kw = dict(WORKLOAD, rho0=rho0)
+def run_gpu(nx, storage, steps, warmup, rho0, diag_every, torch, sclbm, tiling="auto",
+            forcing="shift"):
+    kw = dict(WORKLOAD, rho0=rho0, forcing=forcing)
     sim = sclbm.Simulation(nx, nx, storage=storage, diag_every=diag_every,
                            rho_ref=(0.7, 0.7), tiling=tiling, **kw)
     sim.init_random(1, mean=(0.7, 0.7), amp=0.05)
@@ -244,21 +249,24 @@ def rheology(a, torch, sclbm):
     diagnostics (FP32 storage unless --rheology-storage says otherwise).
     Both coupling sets the paper prints are run: the one listed with the
     rheology experiment (G^r_A = 11.80, G^a_B = -11.70) and the Fig. 2
-    caption set (G^r_A = 11.70, G^a_B = -11.80)."""
+    caption set (G^r_A = 11.70, G^a_B = -11.80), each with the Shan-Chen
+    velocity shift and with Guo forcing."""
     import math
     n, U0, rho0 = 128, 0.1, 0.7
     nu0 = (1.0 - 0.5) / 3.0
     F0 = nu0 * (2 * math.pi / n) ** 2 * U0
-    sets = {"rheology_text": dict(Ga=(-12.55, -11.70), Gr=(11.80, 10.95)),
-            "fig2_caption": dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95))}
+    text = dict(Ga=(-12.55, -11.70), Gr=(11.80, 10.95))
+    caption = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95))
+    sets = {"rheology_text": (text, "shift"), "fig2_caption": (caption, "shift"),
+            "rheology_text_guo": (text, "guo"), "fig2_caption_guo": (caption, "guo")}
     out = {"workload": f"{n}x{n} Kolmogorov flow, U0={U0}, F0={F0:.3e}, G_AB=0.58, "
                        "Psi amplitude sqrt(rho0), rho0=0.7, tau=1, 5% random start, "
                        f"{a.rheology_storage} storage, fused diagnostics every 1000 steps",
            "runs": {}}
-    for name, cp in sets.items():
+    for name, (cp, forcing) in sets.items():
         sim = sclbm.Simulation(n, n, storage=a.rheology_storage, diag_every=1000,
                                tiling="auto", Gx=0.58, rho0=rho0, psi_amp=math.sqrt(rho0),
-                               body_F0=F0, **cp)
+                               body_F0=F0, forcing=forcing, **cp)
         sim.init_random(1)
         chunk = max(1000, a.rheology_steps // 20)
         samples, t_ms, steps = [], 0.0, 0
@@ -273,7 +281,7 @@ def rheology(a, torch, sclbm):
                             "I_AB": round(d["i_ab"], 2), "bad_sites": int(d["bad_sites"])})
         sim.close()
         rs = [x["R"] for x in samples]
-        out["runs"][name] = {"couplings": cp, "steps": steps,
+        out["runs"][name] = {"couplings": cp, "forcing": forcing, "steps": steps,
                              "mlups": round(n * n * steps / (t_ms * 1e-3) / 1e6, 1),
                              "R_min": min(rs), "R_final": rs[-1], "samples": samples}
         log(f"rheology {name}: R_min {min(rs)}, R_final {rs[-1]}")
@@ -509,11 +517,12 @@ def main():
         return
     from paper_0807_4471_amd import sclbm
     nx, storage = a.nx, a.storage
-    sim, ms_total, wall, d = run_gpu(nx, storage, a.steps, a.warmup, a.rho0, 1000, torch, sclbm)
+    sim, ms_total, wall, d = run_gpu(nx, storage, a.steps, a.warmup, a.rho0, 1000, torch, sclbm,
+                                     forcing=a.forcing)
     ms_step = ms_total / a.steps
     mlups = nx * nx / (ms_step * 1e-3) / 1e6
     roof = roofline(nx, storage, ms_step)
-    roof["traffic"] = traffic_for(f"{storage}_{nx}")
+    roof["traffic"] = traffic_for(f"{storage}_{nx}" + ("_guo" if a.forcing == "guo" else ""))
     # ping-pong footprint (2 copies x 18 populations) vs the 256 MiB Infinity Cache
     roof["cache_resident"] = BYTES_PER_LUP[storage] * nx * nx < 256 * 2 ** 20
     out = {
@@ -532,8 +541,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"micro-emulsion {nx}x{nx} periodic two-species D2Q9 "
                                f"Shan-Chen, {storage} populations, rho0={a.rho0}, "
-                               "A=rho0, caption couplings, tau=1, 5% random init",
+                               "A=rho0, caption couplings, tau=1, 5% random init"
+                               + (", Guo forcing" if a.forcing == "guo" else ""),
                    "nx": nx, "ny": nx, "storage": storage, "diag_every": 1000,
+                   "forcing": a.forcing,
                    "tiling": list(sim.get_tiling())},
         "roofline": roof,
         "mass_drift": [float(abs(d["mass"][s] / d["mass0"][s] - 1.0)) for s in (0, 1)],
@@ -545,6 +556,20 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not a.no_guo:
+        other = "guo" if a.forcing == "shift" else "shift"
+        k = max(1000, a.steps // 5)
+        s2, mt, _, d2 = run_gpu(nx, storage, k, a.warmup, a.rho0, 1000, torch, sclbm,
+                                forcing=other)
+        r = roofline(nx, storage, mt / k)
+        out["forcing_variant"] = {
+            "forcing": other, "steps": k, "mlups": round(nx * nx / (mt / k * 1e-3) / 1e6, 1),
+            "ms_per_step": round(mt / k, 6), "frac": r["frac"],
+            "mass_drift": [float(abs(d2["mass"][q] / d2["mass0"][q] - 1.0)) for q in (0, 1)]}
+        log(f"forcing variant: {out['forcing_variant']}")
+        s2.close()
+        del s2
+        torch.cuda.empty_cache()
     if not a.no_dram:
         side = []
         for st_, n_ in (("f32", 4096), ("f16dev", 4096), ("f64", 2048)):

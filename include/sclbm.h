@@ -57,6 +57,7 @@ typedef enum {
 
 enum { SCLBM_PERIODIC = 0, SCLBM_WALLS_Y = 1 };
 enum { SCLBM_F64 = 0, SCLBM_F32 = 1, SCLBM_F16DEV = 2, SCLBM_F16DEV_SR = 3 };
+enum { SCLBM_FORCING_SHIFT = 0, SCLBM_FORCING_GUO = 1 };
 
 /* Lattice, couplings, relaxation times and pseudo-potential of one instance.
  * Copied at bind; the caller may free it afterwards. */
@@ -90,7 +91,15 @@ typedef struct {
     int32_t diag_every;    /* K > 0: fused FP64 diagnostics at every step t with
                               t % K == 0 (read with sclbm_fused_diagnostics);
                               0: off                                               */
-    int32_t reserved;      /* must be 0                                            */
+    int32_t forcing;       /* how the force enters Eq. (1), which the paper leaves
+                              open: SCLBM_FORCING_SHIFT (0): Shan-Chen shift of
+                              the equilibrium velocity, u_eq,s = u' + tau_s F_s /
+                              rho_s with u' = sum_s(j_s/tau_s) / sum_s(rho_s/tau_s);
+                              SCLBM_FORCING_GUO (1): both species relax towards
+                              f^eq(rho_s, u), u = sum_s(j_s + F_s/2) / sum_s rho_s,
+                              and gain Guo's source (1 - 1/(2 tau_s)) w_i
+                              [3 (c_i - u).F_s + 9 (c_i.u)(c_i.F_s)] (momentum
+                              exactly conserved for equal tau_s)                 */
 } sclbm_desc;
 
 /* FP64 totals over the lattice at time `step`. */

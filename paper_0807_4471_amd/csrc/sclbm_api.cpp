@@ -79,7 +79,8 @@ int32_t validate(const sclbm_desc* d)
     if (!finite_pos(d->psi_amp)) return fail(SCLBM_EINVAL, "psi_amp must be finite and > 0");
     if (!isfinite(d->body_F0)) return fail(SCLBM_EINVAL, "body_F0 must be finite");
     if (d->diag_every < 0) return fail(SCLBM_EINVAL, "diag_every must be >= 0");
-    if (d->reserved != 0) return fail(SCLBM_EINVAL, "reserved must be 0");
+    if (d->forcing != SCLBM_FORCING_SHIFT && d->forcing != SCLBM_FORCING_GUO)
+        return fail(SCLBM_EINVAL, "unknown forcing %d", d->forcing);
     // populations are addressed through one buffer resource per species
     // with 32-bit offsets: its 9 planes must span < 2^31 bytes
     const int64_t rows = d->ny + (d->boundary == SCLBM_WALLS_Y ? 2 : 0);
@@ -170,6 +171,8 @@ Coef<A> coefficients(const sclbm_desc* d)
     c.X2 = (A)(gx * W_OF_SHELL[2]);
     c.psi_amp = (A)d->psi_amp;
     c.neg_inv_rho0 = (A)(-1.0 / d->rho0);
+    c.guo = d->forcing == SCLBM_FORCING_GUO;
+    c.pad_ = 0;
     c.body_F0 = d->body_F0;
     c.two_pi_over_ny = 6.283185307179586476925286766559 / (double)d->ny;
     return c;

@@ -57,6 +57,7 @@ struct Coef {
     A wall6u[2];                // 6 u_w (bottom, top): 2 (c_i.u_w)/c_s^2 = 6 c_ix u_w
     A rho_base[2];              // FP16 deviation storage: rho_ref_s (0 otherwise)
     int32_t tau1[2];            // 1 if tau_s == 1 exactly (BGK lands on f^eq)
+    int32_t guo, pad_;          // 1: Guo source term instead of the velocity shift
     double body_F0;             // Kolmogorov amplitude (0 = off)
     double two_pi_over_ny;
 };

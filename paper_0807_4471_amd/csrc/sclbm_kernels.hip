@@ -306,7 +306,8 @@ struct Sweep {
     // representation); v[0] becomes the remainder rhod - sum_{i>0} v_i, so
     // the collision conserves mass to one rounding whatever the rounding of
     // the weights (in FP32 4/9 + 4/9 + 4/36 rounds to 1 + 7.4e-9).
-    __device__ static void bgk(A* v, A rho, A rhod, A ux, A uy, A omega, bool tau1)
+    __device__ static void bgk(A* v, A rho, A rhod, A ux, A uy, A omega, bool tau1, bool guo,
+                               A Fx, A Fy, A tau)
     {
         const A usq15 = A(1.5) * (ux * ux + uy * uy);
         const A w1r = A(W1) * rho, w2r = A(W2) * rho;
@@ -317,9 +318,22 @@ struct Sweep {
             const A P = cu * (A(3) + A(4.5) * cu) - usq15;
             return wr * P + wd;
         };
-        const A eq[9] = {A(0),           veq(w1r, w1d, ux), veq(w1r, w1d, uy),
-                         veq(w1r, w1d, -ux), veq(w1r, w1d, -uy), veq(w2r, w2d, up),
-                         veq(w2r, w2d, -um), veq(w2r, w2d, -up), veq(w2r, w2d, um)};
+        A eq[9] = {A(0),           veq(w1r, w1d, ux), veq(w1r, w1d, uy),
+                   veq(w1r, w1d, -ux), veq(w1r, w1d, -uy), veq(w2r, w2d, up),
+                   veq(w2r, w2d, -um), veq(w2r, w2d, -up), veq(w2r, w2d, um)};
+        if (guo) {
+            // Guo's source (1 - 1/(2 tau)) w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)]
+            // enters as (tau - 1/2) w_i [...] added to the equilibrium, since
+            // omega (tau - 1/2) = 1 - 1/(2 tau).  It carries no mass.
+            const A g3 = A(3) * (tau - A(0.5));
+            const A uf = ux * Fx + uy * Fy;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const A cu = A(CX_[i]) * ux + A(CY_[i]) * uy;
+                const A cf = A(CX_[i]) * Fx + A(CY_[i]) * Fy;
+                eq[i] += (i < 5 ? A(W1) : A(W2)) * g3 * ((cf - uf) + A(3) * cu * cf);
+            }
+        }
         if (tau1) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) v[i] = eq[i];
@@ -449,12 +463,23 @@ struct Sweep {
 
         if constexpr (MODE == M_STEP || MODE == M_STEP_DIAG) {
             // Shan-Chen velocity shift: common velocity weighted by rho_s/tau_s,
-            // species shift tau_s F_s / rho_s.
-            const A den = rho[0] * c.omega[0] + rho[1] * c.omega[1];
-            const A nmx = jx[0] * c.omega[0] + jx[1] * c.omega[1];
-            const A nmy = jy[0] * c.omega[0] + jy[1] * c.omega[1];
-            const A iden = den > A(0) ? rcp<T>(den) : A(0);
-            const A upx = nmx * iden, upy = nmy * iden;
+            // species shift tau_s F_s / rho_s.  Guo forcing instead: the
+            // barycentric velocity with half the force for both species, and
+            // a source term after the relaxation (uniform branch).
+            A upx, upy;
+            if (!c.guo) {
+                const A den = rho[0] * c.omega[0] + rho[1] * c.omega[1];
+                const A nmx = jx[0] * c.omega[0] + jx[1] * c.omega[1];
+                const A nmy = jy[0] * c.omega[0] + jy[1] * c.omega[1];
+                const A iden = den > A(0) ? rcp<T>(den) : A(0);
+                upx = nmx * iden;
+                upy = nmy * iden;
+            } else {
+                const A rt = rho[0] + rho[1];
+                const A irt = rt > A(0) ? rcp<T>(rt) : A(0);
+                upx = ((jx[0] + jx[1]) + A(0.5) * (F[0][0] + F[1][0])) * irt;
+                upy = ((jy[0] + jy[1]) + A(0.5) * (F[0][1] + F[1][1])) * irt;
+            }
             const int ro = y + (WALLS ? 1 : 0);
             const uint32_t soff = (uint32_t)(ro * pitch_b);  // uniform row offsets
             // Wall rows: a population that would leave the channel returns to
@@ -469,9 +494,14 @@ struct Sweep {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 A* f = v + 9 * s;
-                const A ir = rho[s] > A(0) ? c.tau[s] * rcp<T>(rho[s]) : A(0);
-                const A uex = upx + F[s][0] * ir, uey = upy + F[s][1] * ir;
-                bgk(f, rho[s], rhod[s], uex, uey, c.omega[s], c.tau1[s] != 0);
+                A uex = upx, uey = upy;
+                if (!c.guo) {
+                    const A ir = rho[s] > A(0) ? c.tau[s] * rcp<T>(rho[s]) : A(0);
+                    uex += F[s][0] * ir;
+                    uey += F[s][1] * ir;
+                }
+                bgk(f, rho[s], rhod[s], uex, uey, c.omega[s], c.tau1[s] != 0, c.guo != 0,
+                    F[s][0], F[s][1], c.tau[s]);
                 const A corr = A(W2) * rho[s] * u6;  // diagonal Ladd term; axis term is 0
                 [[maybe_unused]] A qsum = A(0);
                 [[maybe_unused]] uint32_t rr = 0;

@@ -22,6 +22,7 @@ F64, F32, F16DEV, F16DEV_SR = 0, 1, 2, 3
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "f16sr": F16DEV_SR}
 BOUNDARY = {"periodic": PERIODIC, "walls": WALLS_Y}
 BYTES_PER_POP = {F64: 8, F32: 4, F16DEV: 2, F16DEV_SR: 2}
+FORCING = {"shift": 0, "guo": 1}
 
 
 class Desc(ctypes.Structure):
@@ -38,7 +39,7 @@ class Desc(ctypes.Structure):
         ("wall_u", ctypes.c_double * 2),
         ("body_F0", ctypes.c_double),
         ("diag_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("forcing", ctypes.c_int32),
     ]
 
 
@@ -144,14 +145,18 @@ def check(status: int, what: str) -> int:
 
 def make_desc(nx, ny, storage="f32", boundary="periodic", tau=(1.0, 1.0),
               Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70, psi_amp=None,
-              rho_ref=(0.7, 0.7), wall_u=(0.0, 0.0), body_F0=0.0, diag_every=0) -> Desc:
-    """Descriptor; defaults are the workload couplings with Psi amplitude rho0."""
+              rho_ref=(0.7, 0.7), wall_u=(0.0, 0.0), body_F0=0.0, diag_every=0,
+              forcing="shift") -> Desc:
+    """Descriptor; defaults are the workload couplings with Psi amplitude rho0.
+    forcing: "shift" (Shan-Chen equilibrium-velocity shift) or "guo"."""
+    if isinstance(forcing, str) and forcing not in FORCING:
+        raise ValueError(f"forcing must be one of {list(FORCING)}")
     return Desc(int(nx), int(ny), BOUNDARY.get(boundary, boundary), STORAGE.get(storage, storage),
                 (ctypes.c_double * 2)(*tau), (ctypes.c_double * 2)(*Ga),
                 (ctypes.c_double * 2)(*Gr), float(Gx), float(rho0),
                 float(rho0 if psi_amp is None else psi_amp),
                 (ctypes.c_double * 2)(*rho_ref), (ctypes.c_double * 2)(*wall_u),
-                float(body_F0), int(diag_every), 0)
+                float(body_F0), int(diag_every), FORCING.get(forcing, forcing))
 
 
 def state_bytes(desc: Desc) -> int:

@@ -8,7 +8,7 @@ import oracle
 from paper_0807_4471_amd import inputs
 
 WORKLOAD = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
-_ORACLE_KEYS = ("tau", "Ga", "Gr", "Gx", "rho0", "psi_amp", "wall_u", "body_F0")
+_ORACLE_KEYS = ("tau", "Ga", "Gr", "Gx", "rho0", "psi_amp", "wall_u", "body_F0", "forcing")
 
 
 def banner(msg: str):

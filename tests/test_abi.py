@@ -66,7 +66,7 @@ def test_state_bytes_scaling(L):
     dict(nx=0), dict(ny=-1), dict(nx=70000), dict(tau=(0.5, 1.0)), dict(tau=(1.0, float("nan"))),
     dict(rho0=0.0), dict(psi_amp=-1.0), dict(Gx=float("inf")), dict(diag_every=-2),
     dict(boundary=7), dict(storage=9), dict(boundary="walls", ny=1),
-    dict(storage="f16dev", rho_ref=(float("nan"), 0.7)),
+    dict(storage="f16dev", rho_ref=(float("nan"), 0.7)), dict(forcing=2), dict(forcing=-1),
 ])
 def test_invalid_descriptors(L, bad):
     kw = dict(nx=32, ny=32)
@@ -122,3 +122,11 @@ def test_bind_errors_and_state(L):
     finally:
         assert L.lib.sclbm_release(h) == L.OK
     assert L.lib.sclbm_release(None) == L.OK
+
+
+def test_forcing_names(L):
+    assert L.make_desc(8, 8, forcing="guo").forcing == 1
+    assert L.make_desc(8, 8).forcing == 0
+    assert L.state_bytes(L.make_desc(8, 8, forcing="guo")) == L.state_bytes(L.make_desc(8, 8))
+    with pytest.raises(ValueError):
+        L.make_desc(8, 8, forcing="he")

@@ -217,3 +217,73 @@ def test_walls_short_lattices_all_tilings(storage, ny, tiling):
     e = max_err(m, ref)
     tol = {"f64": 1e-12, "f32": 1e-4, "f16dev": 1e-2, "f16sr": 1e-2}[storage]
     assert e["rho"] <= tol, e
+
+
+@pytest.mark.parametrize("case", ["workload", "unequal_tau", "body_force", "walls"])
+def test_guo_forcing_f64(case):
+    """Guo forcing (barycentric velocity with half the force, source term
+    (1 - 1/(2 tau)) w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)]) against the oracle."""
+    kw = dict(WORKLOAD, forcing="guo")
+    nx, ny, steps, bound = 48, 40, 60, "periodic"
+    if case == "unequal_tau":
+        kw["tau"] = (0.8, 1.25)
+    elif case == "body_force":
+        kw["body_F0"] = 2e-4
+    elif case == "walls":
+        bound, kw["wall_u"] = "walls", (0.0, 0.06)
+    banner(f"f64 guo {case}")
+    _, m = gpu_run(nx, ny, steps, storage="f64", boundary=bound, **kw)
+    _, _, ref = oracle_run(nx, ny, steps, boundary=bound, **kw)
+    e = max_err(m, ref)
+    print(f"  guo {case}: {e}", flush=True)
+    assert e["rho"] <= 1e-12 and e["u"] <= 1e-12, e
+    # the two couplings differ on this workload (the test would pass vacuously
+    # if the flag were ignored)
+    _, _, shift = oracle_run(nx, ny, steps, boundary=bound,
+                             **{k: v for k, v in kw.items() if k != "forcing"})
+    assert max_err(m, shift)["rho"] > 1e-6
+
+
+def test_guo_forcing_workload_1000_steps_f64():
+    banner("f64 guo 64x64 1000 steps")
+    _, m = gpu_run(64, 64, 1000, storage="f64", forcing="guo", **WORKLOAD)
+    _, _, ref = oracle_run(64, 64, 1000, forcing="guo", **WORKLOAD)
+    e = max_err(m, ref)
+    print(f"  guo 1000 steps: {e}", flush=True)
+    assert e["rho"] <= 1e-10, e
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16dev", 1.5e-4), ("f16sr", 1.5e-4)])
+@pytest.mark.parametrize("tiling", [None, (60, 4, 4, 1), (70, 16, 2, 0)])
+def test_guo_forcing_reduced_precision_one_step(storage, tol, tiling):
+    """One step in reduced-precision storage, both kernel families: the same
+    one-step bounds as the shift coupling."""
+    banner(f"{storage} guo one step tiling={tiling}")
+    _, m = gpu_run(130, 70, 1, storage=storage, tiling=tiling, forcing="guo", **WORKLOAD)
+    _, _, ref = oracle_run(130, 70, 1, forcing="guo", **WORKLOAD)
+    e = max_err(m, ref)
+    print(f"  guo one step {storage}: {e}", flush=True)
+    assert e["rho"] <= tol, e
+
+
+def test_guo_forcing_batch_matches_single():
+    """A batch of Guo and shift instances steps each like its single run."""
+    from paper_0807_4471_amd import inputs, sclbm
+    banner("f32 guo + shift batch")
+    shapes = [(64, 48, "guo"), (100, 30, "shift"), (33, 65, "guo")]
+    singles, members = [], []
+    for i, (nx, ny, fc) in enumerate(shapes):
+        rho = inputs.random_densities(nx, ny, 20 + i)
+        for lst in (singles, members):
+            s = sclbm.Simulation(nx, ny, storage="f32", forcing=fc, **WORKLOAD)
+            s.init_fields(rho)
+            lst.append(s)
+    for s in singles:
+        s.step(25)
+    b = sclbm.Batch(members)
+    b.step(25)
+    for s, t in zip(singles, members):
+        a, c = s.moments(), t.moments()
+        for k in ("rhoA", "rhoB", "ux", "uy"):
+            assert np.array_equal(a[k], c[k]), k
+    b.close()

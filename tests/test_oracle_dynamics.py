@@ -273,3 +273,24 @@ def test_guo_and_shift_agree_without_forces(oracle_lib):
     oracle_lib.run(oracle_lib.Params(**kw), fa, 20)
     oracle_lib.run(oracle_lib.Params(forcing="guo", **kw), fb, 20)
     assert np.abs(fa - fb).max() < 1e-14
+
+
+@pytest.mark.parametrize("amp", [0.70, 0.70 ** 0.5])
+def test_demixing_of_the_workload_needs_the_shift_coupling(oracle_lib, amp):
+    """At the Fig. 2 couplings and tau = 1 the 5% random mixture demixes
+    under the Shan-Chen shift (force drift weighted by tau) but relaxes back
+    to the uniform mixture under Guo forcing (drift weighted by tau - 1/2,
+    as the pressure flux): the micro-emulsion the paper studies needs the
+    shift coupling."""
+    n = 48
+    rho = inputs.random_densities(n, n, 1)
+    s0 = (rho[0] - rho[1]).std()
+    spread = {}
+    for fc in ("shift", "guo"):
+        p = oracle_lib.Params(nx=n, ny=n, psi_amp=amp, forcing=fc, **BJ)
+        f = oracle_lib.init(p, rho)
+        oracle_lib.run(p, f, 1000)
+        r, _, _ = oracle_lib.moments(p, f)
+        spread[fc] = (r[0] - r[1]).std()
+    assert spread["shift"] > 0.5, spread
+    assert spread["guo"] < 0.1 * s0, (spread, s0)

@@ -95,7 +95,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps", type=int, default=250)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     return ap.parse_args()

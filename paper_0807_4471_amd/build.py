@@ -26,13 +26,29 @@ FLAGS = [
 ]
 
 
+# Sources whose code the step kernels are compiled from.
+KERNEL_SOURCES = [os.path.join(CSRC, "sclbm_kernels.hip"), os.path.join(CSRC, "sclbm_internal.h")]
+
+
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace runs collapsed, so
+    that comment and layout edits do not change the hash.  (The kernel
+    sources hold no string literal that contains a comment marker.)"""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Short hash of the kernel source: identifies the code that profiles and
-    counter figures were taken on."""
+    """Short hash of the code of the kernel sources: identifies the code that
+    profiles and counter figures were taken on."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(CSRC, "sclbm_kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for path in KERNEL_SOURCES:
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

@@ -5,7 +5,9 @@
 //   pull-stream f_i(x,t) = f*_i(x - c_i, t-1) -> moments rho_s, j_s ->
 //   Psi_s = A (1 - exp(-rho_s/rho0)) -> Psi/rho halo in LDS -> forces
 //   (24-neighbour like-species stencil, 8-neighbour cross term) ->
-//   Shan-Chen velocity shift -> BGK -> store f*(t).
+//   Shan-Chen velocity shift -> BGK -> store f*(t).  Per instance, Guo's
+//   forcing can replace the shift: BGK towards the equilibrium at the
+//   barycentric velocity (half the force included), plus Guo's source term.
 //
 // Work decomposition.  A workgroup of 64*CW lanes owns a strip of W <=
 // 64*CW - 4 columns (lane <-> column, two halo columns on each side) and

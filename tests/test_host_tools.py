@@ -110,3 +110,15 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_kernel_hash_ignores_comments_not_code(tmp_path, monkeypatch):
+    from paper_0807_4471_amd import build
+    src = tmp_path / "k.hip"
+    src.write_text("int f(int a) { return a + 1; } // one\n/* block\n comment */\n")
+    monkeypatch.setattr(build, "KERNEL_SOURCES", [str(src)])
+    h0 = build.kernel_source_hash()
+    src.write_text("int f(int a)  {\n  return a + 1;   // another comment\n}\n")
+    assert build.kernel_source_hash() == h0
+    src.write_text("int f(int a) { return a + 2; }\n")
+    assert build.kernel_source_hash() != h0

@@ -58,6 +58,20 @@ def random_densities(nx: int, ny: int, seed: int, mean=(0.7, 0.7), amp: float = 
     return m * (1.0 + amp * U)
 
 
+def random_densities_window(nx: int, ny: int, seed: int, ys, xs, mean=(0.7, 0.7),
+                            amp: float = 0.05) -> np.ndarray:
+    """The (2, len(ys), len(xs)) block of random_densities(nx, ny, seed, mean,
+    amp) at rows ys and columns xs (index arrays, e.g. wrapped ranges),
+    drawn without generating the whole lattice."""
+    y = np.asarray(ys, dtype=np.uint64)[:, None]
+    x = np.asarray(xs, dtype=np.uint64)[None, :]
+    n = y * np.uint64(nx) + x
+    c = np.stack([n, n + np.uint64(nx * ny)])
+    U = uniform_pm1(seed, c)
+    m = np.asarray(mean, dtype=np.float64).reshape(2, 1, 1)
+    return m * (1.0 + amp * U)
+
+
 def droplet_densities(nx: int, ny: int, radius: float, rho_in: float, rho_out: float,
                       width: float = 1.5) -> np.ndarray:
     """Static droplet of species A (density rho_in inside) in species B (and

@@ -63,3 +63,31 @@ def structure_factor(phi: np.ndarray):
     ks = np.arange(nsh)
     ok = cnt > 0
     return ks[ok][1:], (tot[ok] / cnt[ok])[1:]
+
+
+def window_half_width(steps: int) -> int:
+    """Half-width of a periodic window whose centre evolves exactly as on the
+    full lattice for `steps` steps and whose velocity read-out is exact: one
+    step reaches 1 site (streaming) + 2 sites (the 25-point Psi stencil),
+    the read-out adds the force stencil (2), plus one site of margin."""
+    return 3 * steps + 2 + 1
+
+
+def oracle_window_moments(nx, ny, seed, sites, steps, mean=(0.7, 0.7), amp=0.05, **kw):
+    """Oracle (rho_A, rho_B, u_x, u_y) at `sites` [(y, x), ...] of the periodic
+    nx x ny lattice initialised by inputs.random_densities(nx, ny, seed),
+    after `steps` steps, each from a periodic window around the site."""
+    okw = {k: v for k, v in kw.items() if k in _ORACLE_KEYS}
+    h = window_half_width(steps)
+    w = 2 * h + 1
+    p = oracle.Params(nx=w, ny=w, **okw)
+    out = []
+    for (y, x) in sites:
+        ys = np.arange(y - h, y + h + 1) % ny
+        xs = np.arange(x - h, x + h + 1) % nx
+        rho = inputs.random_densities_window(nx, ny, seed, ys, xs, mean, amp)
+        f = oracle.init(p, rho)
+        oracle.run(p, f, steps)
+        r, ux, uy = oracle.moments(p, f)
+        out.append((r[0][h, h], r[1][h, h], ux[h, h], uy[h, h]))
+    return np.array(out)

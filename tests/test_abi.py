@@ -130,3 +130,21 @@ def test_forcing_names(L):
     assert L.state_bytes(L.make_desc(8, 8, forcing="guo")) == L.state_bytes(L.make_desc(8, 8))
     with pytest.raises(ValueError):
         L.make_desc(8, 8, forcing="he")
+
+
+@pytest.mark.parametrize("storage,eb,largest", [("f64", 8, 5440), ("f32", 4, 7703),
+                                                ("f16dev", 2, 10901)])
+def test_largest_square_lattice(L, storage, eb, largest):
+    """32-bit offsets: the 9 planes of a species (rows padded to 64
+    elements, plus 128 elements per plane) must span < 2 GiB; the largest
+    accepted square lattice is the last one that fits, the next is
+    EUNSUPPORTED."""
+    def fits(n):
+        return 9 * ((n + 63) // 64 * 64 * n + 128) * eb < 2 ** 31
+    assert fits(largest) and not fits(largest + 1)
+    assert L.state_bytes(L.make_desc(largest, largest, storage=storage)) > 0
+    d = L.make_desc(largest + 1, largest + 1, storage=storage)
+    assert L.state_bytes(d) == 0
+    h = ctypes.c_void_p()
+    rc = L.lib.sclbm_bind(ctypes.byref(d), ctypes.c_void_p(1 << 20), 1 << 40, ctypes.byref(h))
+    assert rc == L.EUNSUPPORTED and not h.value

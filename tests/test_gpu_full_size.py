@@ -65,3 +65,78 @@ def test_4096_uniform_fixed_point(storage):
         assert float(m["ux"].abs().max()) == 0.0
     else:
         assert float(m["ux"].abs().max()) < 1e-4
+
+
+def _edge_sites(n, tile_x, tile_y, seed=0, extra=16):
+    """Sites on strip edges, chunk edges and the lattice edges (where the
+    periodic wrap is taken), plus random ones."""
+    xs = sorted({0, 1, n - 2, n - 1, tile_x - 1, tile_x, 2 * tile_x - 1, 2 * tile_x, n // 2})
+    ys = sorted({0, n - 1, tile_y - 1, tile_y, 2 * tile_y, n // 2 + 1})
+    sites = [(y, x) for y in ys for x in xs if x < n and y < n]
+    rng = np.random.default_rng(seed)
+    sites += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(extra)]
+    return sites
+
+
+@pytest.mark.parametrize("storage,n,tol", [("f32", 4096, 1e-5), ("f16dev", 4096, 6e-4),
+                                           ("f64", 2048, 1e-13)])
+def test_dram_resident_lattices_sampled(storage, n, tol):
+    """The DRAM-resident lattices of the benchmark, in its launch
+    configuration (tuned tiling, fused diagnostics every 1000 steps, so the
+    first step is the diagnostic variant), random start: 3 steps, then
+    densities and velocities at ~70 sites against the oracle run on a
+    periodic window around each site (exact for the window's centre)."""
+    import torch
+    from helpers import oracle_window_moments
+    from paper_0807_4471_amd import sclbm
+    banner(f"{storage} {n}x{n} sampled against windowed oracle")
+    seed, steps = 11, 3
+    sim = sclbm.Simulation(n, n, storage=storage, tiling="auto", diag_every=1000,
+                           rho_ref=(0.7, 0.7), **WORKLOAD)
+    sim.init_random(seed)
+    sim.step(steps)
+    tl = sim.get_tiling()
+    sites = _edge_sites(n, tl[0], tl[1], seed)
+    m = sim.moments_device()
+    iy = torch.tensor([y for y, _ in sites], device=m["rhoA"].device)
+    ix = torch.tensor([x for _, x in sites], device=m["rhoA"].device)
+    got = np.stack([m[k][iy, ix].cpu().numpy() for k in ("rhoA", "rhoB", "ux", "uy")], axis=1)
+    sim.close()
+    ref = oracle_window_moments(n, n, seed, sites, steps, **WORKLOAD)
+    e_rho = float(np.abs(got[:, :2] - ref[:, :2]).max())
+    e_u = float(np.abs(got[:, 2:] - ref[:, 2:]).max())
+    print(f"  tiling {tl}, {len(sites)} sites: max |drho| {e_rho:.3g}, |du| {e_u:.3g}", flush=True)
+    assert e_rho <= tol and e_u <= tol, (e_rho, e_u)
+
+
+@pytest.mark.parametrize("storage,n,tol", [("f32", 7703, 1e-5), ("f16dev", 10901, 6e-4),
+                                           ("f64", 5440, 1e-13)])
+def test_largest_lattices_sampled(storage, n, tol):
+    """The largest square lattice the library accepts per storage type (its
+    species' planes just under the 2 GiB reach of 32-bit offsets; FP32 and
+    FP16 sizes not a multiple of 64): 2 steps, sampled sites against the
+    windowed oracle, including the last row and column."""
+    import torch
+    from helpers import oracle_window_moments
+    from paper_0807_4471_amd import sclbm
+    banner(f"{storage} {n}x{n} (largest accepted) sampled")
+    seed, steps = 12, 2
+    sim = sclbm.Simulation(n, n, storage=storage, tiling="auto", rho_ref=(0.7, 0.7), **WORKLOAD)
+    sim.init_random(seed)
+    sim.step(steps)
+    tl = sim.get_tiling()
+    sites = _edge_sites(n, tl[0], tl[1], seed)
+    m = sim.moments_device()
+    iy = torch.tensor([y for y, _ in sites], device=m["rhoA"].device)
+    ix = torch.tensor([x for _, x in sites], device=m["rhoA"].device)
+    got = np.stack([m[k][iy, ix].cpu().numpy() for k in ("rhoA", "rhoB", "ux", "uy")], axis=1)
+    bad = sim.diagnostics()["bad_sites"]
+    sim.close()
+    del m
+    torch.cuda.empty_cache()
+    ref = oracle_window_moments(n, n, seed, sites, steps, **WORKLOAD)
+    e_rho = float(np.abs(got[:, :2] - ref[:, :2]).max())
+    e_u = float(np.abs(got[:, 2:] - ref[:, 2:]).max())
+    print(f"  tiling {tl}, {len(sites)} sites: max |drho| {e_rho:.3g}, |du| {e_u:.3g}", flush=True)
+    assert bad == 0
+    assert e_rho <= tol and e_u <= tol, (e_rho, e_u)

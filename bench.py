@@ -94,6 +94,12 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-legs", default="step,work,seq",
+                    help="services to run on the trace: step (batched, step-fair), "
+                         "work (batched, work-fair), seq (one at a time, FP64)")
+    ap.add_argument("--serve-capacity-glups", type=float, default=None,
+                    help="batch capacity that sets the arrival rate (default: the "
+                         "measured batch rate, else 20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=250)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -454,23 +460,46 @@ def run_batch(a, torch, sclbm):
 
 def run_serving(a, torch, sclbm, rate_lups):
     from paper_0807_4471_amd import serving
+    if a.serve_capacity_glups:
+        rate_lups = a.serve_capacity_glups * 1e9
     side, steps = (64, 1024), (1000, 100000)
     e_sites = (side[1] ** 2 - side[0] ** 2) / (2.0 * math.log(side[1] / side[0]))
     e_steps = (steps[1] - steps[0]) / math.log(steps[1] / steps[0])
     rate = a.serve_load * rate_lups / (e_sites * e_steps)
     trace = serving.make_trace(a.serve_requests, rate=rate, seed=4242, side=side, steps=steps)
-    r = serving.summarize_public(serving.Server(keep_moments=False).run(trace))
-    log(f"serving (batched, step-fair slices): {r}")
-    r_work = serving.summarize_public(
-        serving.Server(keep_moments=False, slicing="work").run(trace))
-    log(f"serving (batched, work-fair slices): {r_work}")
-    r64 = serving.summarize_public(serving.serve_sequential_f64(trace))
-    log(f"serving (sequential FP64): {r64}")
-    return {"workload": f"{a.serve_requests} Poisson requests at {rate:.3f}/s "
-                        f"(load {a.serve_load} of {rate_lups / 1e9:.1f} GLUPS), sizes 64^2..1024^2 "
-                        "and steps 1e3..1e5 log-uniform, f32 or f16dev, half sheared walls",
-            "arrival_rate_per_s": round(rate, 4), "batched": r, "batched_work_fair": r_work,
-            "sequential_f64": r64}
+    legs = set(a.serve_legs.split(","))
+
+    def progress(name):
+        state = {"done": 0, "last": time.perf_counter()}
+
+        def on_event(kind, rid, t):
+            if kind != "finish":
+                return
+            state["done"] += 1
+            now = time.perf_counter()
+            if now - state["last"] > 30 or state["done"] == len(trace):
+                state["last"] = now
+                log(f"  {name}: {state['done']}/{len(trace)} finished at t={t:.1f} s")
+        return on_event
+
+    out = {"workload": f"{a.serve_requests} Poisson requests at {rate:.3f}/s "
+                       f"(load {a.serve_load} of {rate_lups / 1e9:.1f} GLUPS), sizes 64^2..1024^2 "
+                       "and steps 1e3..1e5 log-uniform, f32 or f16dev, half sheared walls",
+           "arrival_rate_per_s": round(rate, 4)}
+    if "step" in legs:
+        out["batched"] = serving.summarize_public(
+            serving.Server(keep_moments=False).run(trace, on_event=progress("step-fair")))
+        log(f"serving (batched, step-fair slices): {out['batched']}")
+    if "work" in legs:
+        out["batched_work_fair"] = serving.summarize_public(
+            serving.Server(keep_moments=False, slicing="work").run(
+                trace, on_event=progress("work-fair")))
+        log(f"serving (batched, work-fair slices): {out['batched_work_fair']}")
+    if "seq" in legs:
+        out["sequential_f64"] = serving.summarize_public(
+            serving.serve_sequential_f64(trace, on_event=progress("sequential FP64")))
+        log(f"serving (sequential FP64): {out['sequential_f64']}")
+    return out
 
 
 def cpu_baseline(nx, steps, rho0):
@@ -487,7 +516,21 @@ def cpu_baseline(nx, steps, rho0):
     return {"value": round(nx * nx * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
             "kind": "oracle",
             "sample": f"FP64 oracle, {nx}x{nx} periodic, same couplings and seeded init, "
-                      f"{steps} steps ({dt:.1f} s, single thread)"}
+                      f"{steps} steps ({dt:.1f} s, single thread on {host_cpu()})"}
+
+
+def host_cpu() -> str:
+    """Model name of the host CPU, with the number of cores the OS shows."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores visible"
 
 
 def calibrate_copy(torch):

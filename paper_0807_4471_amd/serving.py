@@ -243,9 +243,11 @@ class Server:
         return out
 
 
-def serve_sequential_f64(trace: list[Request], device="cuda", keep_moments=False) -> dict:
+def serve_sequential_f64(trace: list[Request], device="cuda", keep_moments=False,
+                         on_event=None) -> dict:
     """Baseline: the same trace served one request at a time, in arrival
-    order, each on the single-instance FP64 path (sclbm_step)."""
+    order, each on the single-instance FP64 path (sclbm_step).  on_event as
+    for Server.run."""
     import torch
     from . import sclbm
     pending = sorted(trace, key=lambda r: r.arrival)
@@ -257,6 +259,8 @@ def serve_sequential_f64(trace: list[Request], device="cuda", keep_moments=False
         if req.arrival > now:
             time.sleep(req.arrival - now)
         adm = time.perf_counter() - t0
+        if on_event:
+            on_event("admit", req.rid, adm)
         r64 = Request(**{**req.__dict__, "storage": "f64"})
         tc = time.perf_counter()
         sim = _new_sim(r64, device)
@@ -269,6 +273,8 @@ def serve_sequential_f64(trace: list[Request], device="cuda", keep_moments=False
         results[req.rid] = Result(req.rid, req.arrival, adm, fin,
                                   "ok" if d["bad_sites"] == 0 else "failed", mom, d)
         sim.close()
+        if on_event:
+            on_event("finish", req.rid, fin)
     return summarize(trace, results, time.perf_counter() - t0, busy)
 
 

@@ -11,7 +11,8 @@
  * neighbours, weights p_1i and p_2i, 8th-order isotropic) and cross-species
  * repulsion G_AB on the first belt, built from Psi_s[rho] = A(1-exp(-rho/rho0))
  * and from the densities.  The force enters through the Shan-Chen shift of
- * the equilibrium velocity.
+ * the equilibrium velocity or, per instance, through Guo's source term
+ * (sclbm_desc.forcing).
  *
  * Conventions
  *   - Every function returns an int32_t status (sclbm_status); nothing aborts
@@ -190,7 +191,7 @@ int32_t sclbm_init_fields(sclbm_inst* inst, const double* rhoA, const double* rh
                           const double* ux, const double* uy, void* hip_stream);
 
 /* Advance n >= 0 time steps of Eq. (1): one fused stream + moments + Psi +
- * forces + velocity shift + BGK pass per step.  Async. */
+ * forces + velocity shift (or Guo source) + BGK pass per step.  Async. */
 int32_t sclbm_step(sclbm_inst* inst, int64_t n, void* hip_stream);
 
 /* Choose the tiling of sclbm_step for this instance (the library starts

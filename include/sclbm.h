@@ -296,6 +296,16 @@ enum { SCLBM_BATCH_PERSISTENT = 0, SCLBM_BATCH_STEPWISE = 1 };
  * EINVAL for an unknown mode. */
 int32_t sclbm_batch_set_mode(sclbm_batch* batch, int32_t mode);
 
+/* Bound the wait at each grid barrier of later PERSISTENT launches: a
+ * workgroup that has slept `sleeps` times (each ~60 ns plus one coherent
+ * poll) without seeing the barrier complete marks the launch failed and
+ * leaves the kernel, and every other workgroup leaves at its current or
+ * next barrier; sclbm_batch_status then returns EDEVICE and the launch's
+ * results are invalid.  0 restores the default (2^26 sleeps, seconds: far
+ * beyond any real wait).  Small values exist to test the failure path
+ * without a fault or a hang.  Host only; EINVAL for a NULL batch. */
+int32_t sclbm_batch_set_barrier_limit(sclbm_batch* batch, uint32_t sleeps);
+
 /* Launch shape of a planned batch: out[0] = workgroups of this kernel kind
  * that are co-resident on the device (occupancy x compute units), out[1] =
  * tiles per step, out[2] = kernel kind (0: all stacked tiles, 1: all sweep

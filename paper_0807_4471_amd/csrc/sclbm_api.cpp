@@ -680,9 +680,14 @@ int32_t sclbm_restore(sclbm_inst* h, const void* host_buf, size_t bytes, void* s
 
 // ------------------------------------------------------------------ batching
 
+// Sleeps a workgroup waits at one grid barrier before it reports failure:
+// seconds, far beyond any real wait.
+constexpr uint32_t DEFAULT_SPIN_LIMIT = 1u << 26;
+
 struct sclbm_batch {
     int n = 0, storage = 0, nitems = 0, grid = 0, kind = 0, capacity = 0;
     int mode = SCLBM_BATCH_PERSISTENT;
+    uint32_t spin_limit = DEFAULT_SPIN_LIMIT;  // sleeps before a barrier gives up
     std::vector<sclbm_inst*> insts;
     std::vector<sclbm_tiling> tl;
     char* ws = nullptr;
@@ -861,7 +866,8 @@ int32_t sclbm_batch_step(sclbm_batch* b, const int64_t* steps, void* stream)
             e = launch_batch_step(b->storage, b->kind, b->ws, items, b->nitems, s, st);
     } else {
         e = launch_batch(b->storage, b->kind, b->ws, items, b->nitems, max_steps,
-                         reinterpret_cast<BatchCtl*>(b->ws + b->off_ctl), b->grid, st);
+                         reinterpret_cast<BatchCtl*>(b->ws + b->off_ctl), b->spin_limit,
+                         b->grid, st);
     }
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     for (int k = 0; k < b->n; ++k) {
@@ -879,6 +885,13 @@ int32_t sclbm_batch_set_mode(sclbm_batch* b, int32_t mode)
     if (mode != SCLBM_BATCH_PERSISTENT && mode != SCLBM_BATCH_STEPWISE)
         return fail(SCLBM_EINVAL, "unknown batch mode %d", mode);
     b->mode = mode;
+    return SCLBM_OK;
+}
+
+int32_t sclbm_batch_set_barrier_limit(sclbm_batch* b, uint32_t sleeps)
+{
+    if (!b) return fail(SCLBM_EINVAL, "NULL batch");
+    b->spin_limit = sleeps ? sleeps : DEFAULT_SPIN_LIMIT;
     return SCLBM_OK;
 }
 

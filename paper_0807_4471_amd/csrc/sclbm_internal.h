@@ -129,8 +129,11 @@ enum { B_STACKED = 0, B_SWEEP = 1, B_MIXED = 2 };
 // Largest co-resident grid of the batch kernel of this storage and kind, 0 on
 // error.
 int batch_grid(int storage, int kind);
+// Persistent batch launch: max_steps steps in one cooperative launch; a
+// workgroup gives up at a grid barrier after spin_limit sleeps.
 hipError_t launch_batch(int storage, int kind, const void* insts, const BatchItem* items,
-                        int nitems, int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st);
+                        int nitems, int64_t max_steps, BatchCtl* ctl, uint32_t spin_limit,
+                        int grid, hipStream_t st);
 // Step s of every instance with steps > s: one ordinary launch of nitems
 // workgroups (one per item).
 hipError_t launch_batch_step(int storage, int kind, const void* insts, const BatchItem* items,

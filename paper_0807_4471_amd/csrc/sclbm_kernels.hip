@@ -831,9 +831,10 @@ __global__ __launch_bounds__(256) void init_kernel(Inst<typename T::S, typename 
 // agent-scope fences on every lane would invalidate and write back the L2 of
 // the XCD once per poll and per workgroup, which costs about 170 ns per
 // workgroup per barrier (measured: 131 us at 768 workgroups, against 21 us
-// this way).  The wait is bounded: after ~2^26 sleeps the barrier reports
-// failure through ctl->err and every workgroup leaves the kernel.
-__device__ __forceinline__ bool grid_barrier(BatchCtl* ctl)
+// this way).  The wait is bounded: after spin_limit sleeps (the host's
+// choice, normally 2^26) the barrier reports failure through ctl->err, and
+// every workgroup leaves the kernel at its current or next barrier.
+__device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, uint32_t spin_limit)
 {
     __shared__ int ok;
     __syncthreads();
@@ -851,7 +852,7 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl)
             uint32_t spins = 0;
             while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1u << 26) ||
+                if (++spins > spin_limit ||
                     __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     __hip_atomic_store(&ctl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     good = 0;
@@ -923,7 +924,8 @@ __device__ __forceinline__ void batch_item(const BatchInst<typename T::S, typena
 template <class T, int KIND>
 __global__ __launch_bounds__(256) void batch_kernel(
     const BatchInst<typename T::S, typename T::A>* __restrict__ insts,
-    const BatchItem* __restrict__ items, int nitems, int64_t max_steps, BatchCtl* ctl)
+    const BatchItem* __restrict__ items, int nitems, int64_t max_steps, BatchCtl* ctl,
+    uint32_t spin_limit)
 {
     using A2 = typename T::A2;
     __shared__ A2 lpsi[KIND == B_STACKED ? 2 : 6][256];  // stacked tiles use 8 x 64
@@ -937,7 +939,7 @@ __global__ __launch_bounds__(256) void batch_kernel(
             batch_item<T, KIND, false>(bi, it.tile, s, lpsi, lrho, acc);
             __syncthreads();  // the next item reuses the LDS ring
         }
-        if (!grid_barrier(ctl)) return;
+        if (!grid_barrier(ctl, spin_limit)) return;
     }
 }
 
@@ -998,22 +1000,25 @@ int batch_grid(int storage, int kind)
 
 template <class T, int KIND>
 static hipError_t batch_go(const void* insts, const BatchItem* items, int nitems,
-                           int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st)
+                           int64_t max_steps, BatchCtl* ctl, uint32_t spin_limit, int grid,
+                           hipStream_t st)
 {
     auto bi = static_cast<const BatchInst<typename T::S, typename T::A>*>(insts);
-    void* args[] = {(void*)&bi, (void*)&items, (void*)&nitems, (void*)&max_steps, (void*)&ctl};
+    void* args[] = {(void*)&bi,        (void*)&items, (void*)&nitems, (void*)&max_steps,
+                    (void*)&ctl,       (void*)&spin_limit};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&batch_kernel<T, KIND>),
                                       dim3(grid), dim3(256), args, 0, st);
 }
 
 template <class T>
 static hipError_t batch_go_k(int kind, const void* insts, const BatchItem* items, int nitems,
-                             int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st)
+                             int64_t max_steps, BatchCtl* ctl, uint32_t lim, int grid,
+                             hipStream_t st)
 {
     switch (kind) {
-    case B_STACKED: return batch_go<T, B_STACKED>(insts, items, nitems, max_steps, ctl, grid, st);
-    case B_SWEEP: return batch_go<T, B_SWEEP>(insts, items, nitems, max_steps, ctl, grid, st);
-    case B_MIXED: return batch_go<T, B_MIXED>(insts, items, nitems, max_steps, ctl, grid, st);
+    case B_STACKED: return batch_go<T, B_STACKED>(insts, items, nitems, max_steps, ctl, lim, grid, st);
+    case B_SWEEP: return batch_go<T, B_SWEEP>(insts, items, nitems, max_steps, ctl, lim, grid, st);
+    case B_MIXED: return batch_go<T, B_MIXED>(insts, items, nitems, max_steps, ctl, lim, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -1054,13 +1059,15 @@ hipError_t launch_batch_step(int storage, int kind, const void* insts, const Bat
 }
 
 hipError_t launch_batch(int storage, int kind, const void* insts, const BatchItem* items,
-                        int nitems, int64_t max_steps, BatchCtl* ctl, int grid, hipStream_t st)
+                        int nitems, int64_t max_steps, BatchCtl* ctl, uint32_t spin_limit,
+                        int grid, hipStream_t st)
 {
+    const uint32_t L = spin_limit;
     switch (storage) {
-    case 0: return batch_go_k<TF64>(kind, insts, items, nitems, max_steps, ctl, grid, st);
-    case 1: return batch_go_k<TF32>(kind, insts, items, nitems, max_steps, ctl, grid, st);
-    case 2: return batch_go_k<TF16>(kind, insts, items, nitems, max_steps, ctl, grid, st);
-    case 3: return batch_go_k<TF16SR>(kind, insts, items, nitems, max_steps, ctl, grid, st);
+    case 0: return batch_go_k<TF64>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
+    case 1: return batch_go_k<TF32>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
+    case 2: return batch_go_k<TF16>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
+    case 3: return batch_go_k<TF16SR>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
     }
     return hipErrorInvalidValue;
 }

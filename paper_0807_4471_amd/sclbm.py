@@ -118,6 +118,7 @@ def _load():
         "sclbm_batch_release": ([vp], i32),
         "sclbm_batch_info": ([vp, ctypes.POINTER(i32)], i32),
         "sclbm_batch_set_mode": ([vp, i32], i32),
+        "sclbm_batch_set_barrier_limit": ([vp, ctypes.c_uint32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -385,6 +386,12 @@ class Batch:
 
     def status(self, stream=None):
         check(lib.sclbm_batch_status(self._h, _stream(stream)), "batch_status")
+
+    def set_barrier_limit(self, sleeps: int = 0):
+        """Sleeps a workgroup of the persistent mode waits at one grid barrier
+        before the launch is reported failed (0: the default, seconds)."""
+        check(lib.sclbm_batch_set_barrier_limit(self._h, int(sleeps)), "batch_set_barrier_limit")
+        return self
 
     def info(self) -> dict:
         """capacity: co-resident workgroups of this kernel kind; tiles per

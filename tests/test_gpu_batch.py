@@ -91,3 +91,33 @@ def test_batch_rejects_bad_plans():
         sclbm.Batch([a], [(60, 8, 2, 0)])          # waves != 4
     with pytest.raises(sclbm.SclbmError):
         sclbm.Batch([a], [(61, 4, 4, 1)])          # stacked tile too wide
+
+
+def test_barrier_time_out_is_reported_and_recoverable():
+    """Force the persistent mode's grid-barrier time-out from the host (a
+    limit of one sleep, while the uneven instances make workgroups wait
+    microseconds): every workgroup still leaves the kernel, the batch
+    reports EDEVICE, and with the default limit restored the next launch
+    gives the results of running alone."""
+    from paper_0807_4471_amd import sclbm
+    banner("persistent batch: forced barrier time-out, then recovery")
+    cases = CASES + [(768, 768, "periodic", {})]   # many more tiles than workgroups
+    sims = [_make("f32", *c, seed=60 + k) for k, c in enumerate(cases)]
+    b = sclbm.Batch(sims, mode="persistent")
+    info = b.info()
+    assert info["tiles"] > 2 * info["grid"], info
+    b.set_barrier_limit(1)
+    b.step([20] * len(sims))
+    with pytest.raises(sclbm.SclbmError) as ei:
+        b.status()
+    assert ei.value.status == sclbm.EDEVICE
+    b.set_barrier_limit(0)
+    for k, s in enumerate(sims):
+        s.init_random(60 + k)
+    b.step([9] * len(sims))
+    b.status()
+    for k, c in enumerate(cases):
+        alone = _make("f32", *c, seed=60 + k)
+        alone.step(9)
+        assert np.array_equal(alone.moments()["rhoA"], sims[k].moments()["rhoA"]), k
+    b.close()

@@ -37,9 +37,12 @@
  * 8th-order isotropy of the repulsion stencil; zero net force; mass and
  * momentum conservation; uniform state; shear-wave viscosity
  * c_s^2 (tau - 1/2); exact Couette profile between walls; Galilean advection;
- * Laplace law dP ~ 1/R.  The physical-velocity and sigma_xy read-outs are
- * readings of the paper with no independent pin beyond the G = 0 textbook
- * cases ("parity unpinned" for the multi-species stress definition).
+ * Laplace law dP ~ 1/R.  The read-outs (physical velocity with the half
+ * force, sigma_xy, totals, row profiles, u_bar, I_AB) are checked with forces
+ * and a body force on against a whole-array brute-force evaluation of their
+ * definitions on tiny lattices, periodic and with walls.  Those definitions
+ * are readings (the paper gives neither); the G = 0 textbook cases (exact
+ * Couette velocity and stress) confirm them physically.
  */
 #include "sclbm_oracle.h"
 

@@ -60,8 +60,9 @@ def feq_all(W, rho, ux, uy):
     return W[:, None, None] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
 
 
-def step(f, prm):
-    """One step of f[s, i, y, x] (post-stream populations at t) -> t + 1."""
+def forces(f, prm):
+    """Moments and forces of the state f[s, i, y, x]: rho[s], jx[s], jy[s],
+    F[s, component] (interaction plus body force)."""
     W, wsh, psh = _weights()
     walls = prm["walls"]
     ny, nx = f.shape[2:]
@@ -86,6 +87,15 @@ def step(f, prm):
         if prm["F0"]:
             y = np.arange(ny)[:, None]
             F[s, 0] += rho[s] * prm["F0"] * np.sin(2.0 * np.pi * y / ny)
+    return rho, jx, jy, F
+
+
+def step(f, prm):
+    """One step of f[s, i, y, x] (post-stream populations at t) -> t + 1."""
+    W, _, _ = _weights()
+    walls = prm["walls"]
+    ny, nx = f.shape[2:]
+    rho, jx, jy, F = forces(f, prm)
     tau = prm["tau"]
     guo = prm.get("forcing", "shift") == "guo"
     if guo:   # barycentric velocity with half the force
@@ -180,3 +190,67 @@ def test_a_planted_mistake_is_caught(oracle_lib):
     for _ in range(2):
         f_bad = step(f_bad, bad)
     assert np.abs(f_or - f_bad).max() > 1e-6
+
+
+def readouts(f, prm, half_force=True):
+    """Every read-out of the state f at time t, from the definitions:
+    physical velocity u = (sum_s j_s + F_s/2) / sum_s rho_s; deviatoric
+    stress sigma_xy = -sum_s (1 - 1/(2 tau_s)) sum_i c_ix c_iy (f_is -
+    f^eq_i(rho_s, u)); lattice totals; row means; the Kolmogorov-mode
+    amplitude of u_x and grad rho_A . grad rho_B with the D2Q9 gradient
+    3 sum_i w_i c_i rho(x + c_i) (neighbours wrapped, or mirrored at walls)."""
+    W, _, _ = _weights()
+    ny, nx = f.shape[2:]
+    rho, jx, jy, F = forces(f, prm)
+    h = 0.5 if half_force else 0.0
+    rt = rho.sum(axis=0)
+    ux = (jx.sum(axis=0) + h * F[:, 0].sum(axis=0)) / rt
+    uy = (jy.sum(axis=0) + h * F[:, 1].sum(axis=0)) / rt
+    sxy = np.zeros((ny, nx))
+    for s in range(2):
+        neq = f[s] - feq_all(W, rho[s], ux, uy)
+        sxy -= (1.0 - 0.5 / prm["tau"][s]) * np.tensordot(CX * CY, neq, axes=([0], [0]))
+    y = np.arange(ny)[:, None]
+    u_bar = 2.0 / (nx * ny) * float((ux * np.sin(2.0 * np.pi * y / ny)).sum())
+    grads = []
+    for s in range(2):
+        gx = sum(3.0 * W[i] * CX[i] * _shift(rho[s], CX[i], CY[i], prm["walls"]) for i in range(9))
+        gy = sum(3.0 * W[i] * CY[i] * _shift(rho[s], CX[i], CY[i], prm["walls"]) for i in range(9))
+        grads.append((gx, gy))
+    i_ab = float((grads[0][0] * grads[1][0] + grads[0][1] * grads[1][1]).sum())
+    mom = (jx.sum(axis=0) + 0.5 * F[:, 0].sum(axis=0)).sum(), \
+        (jy.sum(axis=0) + 0.5 * F[:, 1].sum(axis=0)).sum()
+    return dict(rho=rho, ux=ux, uy=uy, sxy=sxy, mass=rho.sum(axis=(1, 2)), mom=np.array(mom),
+                sxy_total=sxy.sum(), ux_row=ux.mean(axis=1), sxy_row=sxy.mean(axis=1),
+                u_bar=u_bar, i_ab=i_ab)
+
+
+@pytest.mark.parametrize("forcing", ["shift", "guo"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_readouts_match_brute_force(oracle_lib, walls, forcing):
+    """Moments (with the half-force velocity), sigma_xy, totals, row
+    profiles, u_bar and I_AB of an evolved state with forces and a body
+    force on, against the definitions evaluated on whole arrays."""
+    nx, ny = 9, 8
+    oracle, p, prm, f = _case(nx, ny, walls, seed=17, F0=3e-3,
+                              wall_u=(0.01, -0.04) if walls else (0.0, 0.0), forcing=forcing)
+    oracle.run(p, f, 4)
+    bf = readouts(f, prm)
+    r, ux, uy = oracle.moments(p, f)
+    tol = 1e-13
+    assert np.abs(r - bf["rho"]).max() <= tol
+    assert np.abs(ux - bf["ux"]).max() <= tol and np.abs(uy - bf["uy"]).max() <= tol
+    tot = oracle.totals(p, f)
+    assert np.allclose(tot["mass"], bf["mass"], rtol=1e-14, atol=0)
+    assert np.abs(tot["mom"] - bf["mom"]).max() <= 1e-12
+    assert abs(tot["sxy"] - bf["sxy_total"]) <= 1e-12
+    ux_row, sxy_row = oracle.row_profiles(p, f)
+    assert np.abs(ux_row - bf["ux_row"]).max() <= tol
+    assert np.abs(sxy_row - bf["sxy_row"]).max() <= tol
+    assert np.abs(sxy_row).max() > 1e-4          # the stress read-out is exercised
+    sf = oracle.shear_flow(p, f)
+    assert abs(sf["u_bar"] - bf["u_bar"]) <= tol
+    assert abs(sf["i_ab"] - bf["i_ab"]) <= 1e-12 * max(1.0, abs(bf["i_ab"]))
+    # the half-force term is visible at this size: dropping it is caught
+    no_half = readouts(f, prm, half_force=False)
+    assert np.abs(ux - no_half["ux"]).max() > 1e-6

@@ -254,3 +254,24 @@ def test_readouts_match_brute_force(oracle_lib, walls, forcing):
     # the half-force term is visible at this size: dropping it is caught
     no_half = readouts(f, prm, half_force=False)
     assert np.abs(ux - no_half["ux"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_init_is_the_equilibrium_of_the_given_fields(oracle_lib, walls):
+    """f_is(x, 0) = f^eq_i(rho_s(x), u(x)) at every site, in the oracle's
+    [s][i][y][x] layout (the step tests start both sides from this state, so
+    they cannot see a mistake in it)."""
+    import oracle
+    W, _, _ = _weights()
+    nx, ny = 7, 6
+    p = oracle.Params(nx=nx, ny=ny, walls=walls)
+    rho = inputs.random_densities(nx, ny, 23, amp=0.3)
+    rng = np.random.default_rng(23)
+    ux, uy = 0.1 * rng.standard_normal((2, ny, nx))
+    f = oracle.init(p, rho, ux, uy)
+    assert f.shape == (2, 9, ny, nx)
+    for s in range(2):
+        assert np.abs(f[s] - feq_all(W, rho[s], ux, uy)).max() <= 1e-15
+    f0 = oracle.init(p, rho)                     # velocity omitted: at rest
+    for s in range(2):
+        assert np.abs(f0[s] - feq_all(W, rho[s], 0.0 * ux, 0.0 * uy)).max() <= 1e-15

@@ -80,6 +80,7 @@ def parse():
                     help="skip the Guo-forcing side run of the headline workload")
     ap.add_argument("--no-sweep", action="store_true", help="skip the rho0 sweep")
     ap.add_argument("--no-dram", action="store_true", help="skip the DRAM-resident side runs")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64x64 FP64 case")
     ap.add_argument("--no-shear", action="store_true", help="skip the sheared-cell object")
     ap.add_argument("--shear-steps", type=int, default=50000)
     ap.add_argument("--no-rheology", action="store_true", help="skip the Kolmogorov-flow run")
@@ -178,6 +179,26 @@ def structure_peak(torch, sim):
     Sk[0] = 0.0
     k = int(np.argmax(Sk))
     return {"k_peak": k, "S_peak": float(Sk[k])}
+
+
+def small_f64(torch, sclbm):
+    """The plain FP64 case: 64x64 periodic, caption couplings, A = rho0 = 0.7,
+    tau = 1, seed 1, 1000 steps (its parity with the oracle is a test)."""
+    sim = sclbm.Simulation(64, 64, storage="f64", tiling="auto", **WORKLOAD)
+    sim.init_random(1)
+    m0 = sim.diagnostics()["mass"]
+    steps = 1000
+    ms, _ = timed(torch, lambda: sim.step(steps))
+    d = sim.diagnostics()
+    step_s = ms * 1e-3 / steps
+    out = {"workload": "64x64 periodic FP64, caption couplings, A=rho0=0.7, tau=1, seed 1",
+           "steps": steps, "us_per_step": round(step_s * 1e6, 3),
+           "mlups": round(64 * 64 / step_s / 1e6, 1),
+           "mass_drift": [float(abs(d["mass"][s] / m0[s] - 1.0)) for s in (0, 1)],
+           "tiling": list(sim.get_tiling())}
+    sim.close()
+    log(f"small f64: {out}")
+    return out
 
 
 def rho0_sweep(a, torch, sclbm, head):
@@ -613,6 +634,8 @@ def main():
         s2.close()
         del s2
         torch.cuda.empty_cache()
+    if not a.no_small:
+        out["small_f64"] = small_f64(torch, sclbm)
     if not a.no_dram:
         side = []
         for st_, n_ in (("f32", 4096), ("f16dev", 4096), ("f64", 2048)):

@@ -122,9 +122,10 @@ def timed(torch, fn):
 
 
 def run_gpu(nx, storage, steps, warmup, rho0, diag_every, torch, sclbm, tiling="auto",
-            forcing="shift"):
+            forcing="shift", ny=None):
     kw = dict(WORKLOAD, rho0=rho0, forcing=forcing)
-    sim = sclbm.Simulation(nx, nx, storage=storage, diag_every=diag_every,
+    ny = nx if ny is None else ny
+    sim = sclbm.Simulation(nx, ny, storage=storage, diag_every=diag_every,
                            rho_ref=(0.7, 0.7), tiling=tiling, **kw)
     sim.init_random(1, mean=(0.7, 0.7), amp=0.05)
     d0 = sim.diagnostics()
@@ -135,13 +136,13 @@ def run_gpu(nx, storage, steps, warmup, rho0, diag_every, torch, sclbm, tiling="
     return sim, ms_total, wall, d
 
 
-def roofline(nx, storage, kernel_ms):
+def roofline(nx, storage, kernel_ms, ny=None):
     """Roofline of the fused step kernel.  kernel_ms is its average launch
     duration: the HIP-event time of the timed region on the launch stream
     divided by the number of step launches (the launches run back to back;
     the diagnostics reductions inside the region add < 0.1%).  Algorithmic
     bytes: every site reads and writes 18 populations once."""
-    alg = BYTES_PER_LUP[storage] * nx * nx
+    alg = BYTES_PER_LUP[storage] * nx * (nx if ny is None else ny)
     achieved = alg / (kernel_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
@@ -638,12 +639,15 @@ def main():
         out["small_f64"] = small_f64(torch, sclbm)
     if not a.no_dram:
         side = []
-        for st_, n_ in (("f32", 4096), ("f16dev", 4096), ("f64", 2048)):
-            s2, mt, _, _ = run_gpu(n_, st_, 200, 20, a.rho0, 0, torch, sclbm)
-            r = roofline(n_, st_, mt / 200)
-            r["traffic"] = traffic_for(f"{st_}_{n_}")
-            side.append({"workload": f"{n_}x{n_} {st_} (DRAM-resident)",
-                         "mlups": round(n_ * n_ / (mt / 200 * 1e-3) / 1e6, 1), "roofline": r,
+        for st_, n_, m_ in (("f32", 4096, 4096), ("f16dev", 4096, 4096), ("f64", 2048, 2048),
+                            ("f32", 8192, 1024), ("f16dev", 8192, 1024)):
+            s2, mt, _, _ = run_gpu(n_, st_, 200, 20, a.rho0, 0, torch, sclbm, ny=m_)
+            r = roofline(n_, st_, mt / 200, ny=m_)
+            r["traffic"] = traffic_for(f"{st_}_{n_}" if n_ == m_ else f"{st_}_{n_}x{m_}")
+            what = "(DRAM-resident)" if n_ == m_ else \
+                "(one GPU's slab of a lattice split by rows, DRAM-resident)"
+            side.append({"workload": f"{n_}x{m_} {st_} {what}",
+                         "mlups": round(n_ * m_ / (mt / 200 * 1e-3) / 1e6, 1), "roofline": r,
                          "tiling": list(s2.get_tiling())})
             log(f"dram: {side[-1]}")
             s2.close()

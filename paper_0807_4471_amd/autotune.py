@@ -325,18 +325,25 @@ def tune_batch(mixes, steps: int | None = None, table: dict | None = None,
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 256, 512, 1024, 2048, 4096])
+    ap.add_argument("--shapes", nargs="+", default=[],
+                    help="rectangular lattices NXxNY to tune instead of the square sizes "
+                         "(e.g. 8192x1024, one GPU's slab of a lattice split by rows)")
     ap.add_argument("--storage", nargs="+", default=["f32", "f16dev", "f64"])
     ap.add_argument("--boundary", nargs="+", default=["periodic"])
     ap.add_argument("--batch", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args()
     table = load_table()
+    if a.shapes:
+        shapes = [tuple(int(v) for v in sh.lower().split("x")) for sh in a.shapes]
+    else:
+        shapes = [(n, n) for n in a.sizes]
     for st in a.storage:
         for bc in a.boundary:
-            for n in a.sizes:
-                best = tune(n, n, st, bc, batch=a.batch, table=table, verbose=a.verbose)
-                e = table[key(n, n, st, bc, a.batch)]
-                print(f"{key(n, n, st, bc, a.batch)}: {best}  {e['us_per_step']} us/step  "
+            for nx, ny in shapes:
+                best = tune(nx, ny, st, bc, batch=a.batch, table=table, verbose=a.verbose)
+                e = table[key(nx, ny, st, bc, a.batch)]
+                print(f"{key(nx, ny, st, bc, a.batch)}: {best}  {e['us_per_step']} us/step  "
                       f"{e['mlups']} MLUPS", flush=True)
                 save_table(table)
 

@@ -149,6 +149,14 @@ def roofline(nx, storage, kernel_ms, ny=None):
             "alg_bytes_per_launch": alg, "kernel_us": round(kernel_ms * 1e3, 3)}
 
 
+def with_traffic(r: dict, traffic):
+    """Attach the counter bytes per launch and the rate they imply."""
+    r["traffic"] = traffic
+    if traffic:
+        r["traffic_GBps"] = round(traffic / (r["kernel_us"] * 1e-6) / 1e9, 1)
+    return r
+
+
 def traffic_for(key: str):
     """Bytes per launch between L2 and the memory fabric, from committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain copy, if they
@@ -587,7 +595,7 @@ def main():
     ms_step = ms_total / a.steps
     mlups = nx * nx / (ms_step * 1e-3) / 1e6
     roof = roofline(nx, storage, ms_step)
-    roof["traffic"] = traffic_for(f"{storage}_{nx}" + ("_guo" if a.forcing == "guo" else ""))
+    with_traffic(roof, traffic_for(f"{storage}_{nx}" + ("_guo" if a.forcing == "guo" else "")))
     # ping-pong footprint (2 copies x 18 populations) vs the 256 MiB Infinity Cache
     roof["cache_resident"] = BYTES_PER_LUP[storage] * nx * nx < 256 * 2 ** 20
     out = {
@@ -643,7 +651,7 @@ def main():
                             ("f32", 8192, 1024), ("f16dev", 8192, 1024)):
             s2, mt, _, _ = run_gpu(n_, st_, 200, 20, a.rho0, 0, torch, sclbm, ny=m_)
             r = roofline(n_, st_, mt / 200, ny=m_)
-            r["traffic"] = traffic_for(f"{st_}_{n_}" if n_ == m_ else f"{st_}_{n_}x{m_}")
+            with_traffic(r, traffic_for(f"{st_}_{n_}" if n_ == m_ else f"{st_}_{n_}x{m_}"))
             what = "(DRAM-resident)" if n_ == m_ else \
                 "(one GPU's slab of a lattice split by rows, DRAM-resident)"
             side.append({"workload": f"{n_}x{m_} {st_} {what}",

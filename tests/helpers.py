@@ -16,10 +16,12 @@ def banner(msg: str):
 
 
 def gpu_run(nx, ny, steps, rho=None, ux=None, uy=None, seed=1, tiling=None, **kw):
-    """Returns (Simulation, moments dict) after `steps` steps."""
+    """Returns (Simulation, moments dict) after `steps` steps.  tiling: None
+    (library default), "auto" (the tuned table, as the benchmark runs) or a
+    tuple."""
     from paper_0807_4471_amd import sclbm
-    sim = sclbm.Simulation(nx, ny, **kw)
-    if tiling is not None:
+    sim = sclbm.Simulation(nx, ny, tiling="auto" if tiling == "auto" else None, **kw)
+    if tiling is not None and tiling != "auto":
         sim.set_tiling(*tiling)
     if rho is None:
         rho = inputs.random_densities(nx, ny, seed)

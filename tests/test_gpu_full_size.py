@@ -10,10 +10,12 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("rho0", [0.60, 0.70, 0.75])
 def test_512_f32_all_sites(rho0):
-    """512x512 FP32 (the micro-emulsion workload), every site after 10 steps."""
+    """512x512 FP32 (the micro-emulsion workload) in the benchmark's launch
+    configuration (tuned tiling, fused diagnostics on the first step), every
+    site after 10 steps."""
     kw = dict(WORKLOAD, rho0=rho0)
     banner(f"f32 512x512 rho0={rho0} 10 steps")
-    _, m = gpu_run(512, 512, 10, storage="f32", **kw)
+    _, m = gpu_run(512, 512, 10, storage="f32", tiling="auto", diag_every=1000, **kw)
     _, _, ref = oracle_run(512, 512, 10, **kw)
     e = max_err(m, ref)
     print(f"  512^2 f32 error: {e}", flush=True)
@@ -78,9 +80,11 @@ def _edge_sites(n, tile_x, tile_y, seed=0, extra=16):
     return sites
 
 
-@pytest.mark.parametrize("storage,n,tol", [("f32", 4096, 1e-5), ("f16dev", 4096, 6e-4),
-                                           ("f64", 2048, 1e-13)])
-def test_dram_resident_lattices_sampled(storage, n, tol):
+@pytest.mark.parametrize("storage,n,tol,forcing", [("f32", 4096, 1e-5, "shift"),
+                                                   ("f16dev", 4096, 6e-4, "shift"),
+                                                   ("f64", 2048, 1e-13, "shift"),
+                                                   ("f32", 4096, 1e-5, "guo")])
+def test_dram_resident_lattices_sampled(storage, n, tol, forcing):
     """The DRAM-resident lattices of the benchmark, in its launch
     configuration (tuned tiling, fused diagnostics every 1000 steps, so the
     first step is the diagnostic variant), random start: 3 steps, then
@@ -89,10 +93,10 @@ def test_dram_resident_lattices_sampled(storage, n, tol):
     import torch
     from helpers import oracle_window_moments
     from paper_0807_4471_amd import sclbm
-    banner(f"{storage} {n}x{n} sampled against windowed oracle")
+    banner(f"{storage} {n}x{n} {forcing} sampled against windowed oracle")
     seed, steps = 11, 3
     sim = sclbm.Simulation(n, n, storage=storage, tiling="auto", diag_every=1000,
-                           rho_ref=(0.7, 0.7), **WORKLOAD)
+                           rho_ref=(0.7, 0.7), forcing=forcing, **WORKLOAD)
     sim.init_random(seed)
     sim.step(steps)
     tl = sim.get_tiling()
@@ -102,11 +106,23 @@ def test_dram_resident_lattices_sampled(storage, n, tol):
     ix = torch.tensor([x for _, x in sites], device=m["rhoA"].device)
     got = np.stack([m[k][iy, ix].cpu().numpy() for k in ("rhoA", "rhoB", "ux", "uy")], axis=1)
     sim.close()
-    ref = oracle_window_moments(n, n, seed, sites, steps, **WORKLOAD)
+    ref = oracle_window_moments(n, n, seed, sites, steps, forcing=forcing, **WORKLOAD)
     e_rho = float(np.abs(got[:, :2] - ref[:, :2]).max())
     e_u = float(np.abs(got[:, 2:] - ref[:, 2:]).max())
     print(f"  tiling {tl}, {len(sites)} sites: max |drho| {e_rho:.3g}, |du| {e_u:.3g}", flush=True)
     assert e_rho <= tol and e_u <= tol, (e_rho, e_u)
+
+
+def test_512_f32_guo_all_sites():
+    """The headline lattice in the benchmark's launch configuration, with Guo
+    forcing: every site after 10 steps."""
+    kw = dict(WORKLOAD, forcing="guo")
+    banner("f32 512x512 guo 10 steps")
+    _, m = gpu_run(512, 512, 10, storage="f32", tiling="auto", diag_every=1000, **kw)
+    _, _, ref = oracle_run(512, 512, 10, **kw)
+    e = max_err(m, ref)
+    print(f"  512^2 f32 guo error: {e}", flush=True)
+    assert e["rho"] <= 10 * 1e-6, e
 
 
 @pytest.mark.parametrize("storage,n,tol", [("f32", 7703, 1e-5), ("f16dev", 10901, 6e-4),

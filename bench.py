@@ -626,6 +626,14 @@ def main():
     log(f"headline: {out['value']} MLUPS, {roof['kernel_us']} us/step, frac {roof['frac']}")
     if not a.no_sweep:
         out["rho0_sweep"] = rho0_sweep(a, torch, sclbm, (sim, ms_total, d))
+    # run-to-run spread: five more timed regions of 20k steps on the same
+    # lattice (after the sweep has read its state)
+    reps = sorted(timed(torch, lambda: sim.step(20000))[0] / 20000 for _ in range(5))
+    out["repeats"] = {"runs": 5, "steps_each": 20000,
+                      "median_us_per_step": round(reps[2] * 1e3, 3),
+                      "min_us_per_step": round(reps[0] * 1e3, 3),
+                      "max_us_per_step": round(reps[-1] * 1e3, 3)}
+    log(f"headline repeats: {out['repeats']}")
     sim.close()
     del sim
     torch.cuda.empty_cache()

@@ -41,6 +41,9 @@ def test_bench_line_contract():
     assert abs(rf["achieved"] - 144 * 512 * 512 / (d["ms_per_step"] * 1e-3) / 1e9) \
         <= 0.01 * rf["achieved"]
     assert rf["traffic"] is None or rf["traffic"] > 0
+    rp = d["repeats"]
+    assert rp["runs"] == 5
+    assert rp["min_us_per_step"] <= rp["median_us_per_step"] <= rp["max_us_per_step"]
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["unit"] == "MLUPS" and cb["cores"] == 1
     assert cb["value"] > 0 and "3 steps" in cb["sample"]

@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--ageing-members", type=int, default=16)
     ap.add_argument("--no-laplace", action="store_true", help="skip the sigma(rho0) sweep")
     ap.add_argument("--laplace-steps", type=int, default=10000)
+    ap.add_argument("--laplace-forcing", default="shift", choices=["shift", "guo"],
+                    help="force coupling of the droplets of the sigma(rho0) sweep")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
@@ -394,7 +396,8 @@ def laplace_sweep(a, torch, sclbm):
             amp = r0 if amp_name == "rho0" else math.sqrt(r0)
             params = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=r0, psi_amp=amp)
             for R in radii:
-                sims.append(sclbm.Simulation(L, L, storage="f64", **params).init_fields(
+                sims.append(sclbm.Simulation(L, L, storage="f64", forcing=a.laplace_forcing,
+                                             **params).init_fields(
                     inputs.droplet_densities(L, L, R, 1.5, 0.06)))
                 cases.append((amp_name, r0, R, params))
     b = sclbm.Batch(sims, "auto")
@@ -406,7 +409,8 @@ def laplace_sweep(a, torch, sclbm):
         pts.setdefault((amp_name, r0), []).append(droplet_jump(m["rhoA"], m["rhoB"], params))
         sim.close()
     out = {"workload": f"{len(sims)} static droplets on {L}x{L} (radii {radii}), caption "
-                       f"couplings, FP64, {a.laplace_steps} steps in one batch",
+                       f"couplings, FP64, {a.laplace_forcing} forcing, {a.laplace_steps} "
+                       "steps in one batch",
            "batched_mlups": round(len(sims) * L * L * a.laplace_steps / (ms * 1e-3) / 1e6, 1),
            "sigma": {}}
     def num(v, k):

@@ -294,3 +294,25 @@ def test_demixing_of_the_workload_needs_the_shift_coupling(oracle_lib, amp):
         spread[fc] = (r[0] - r[1]).std()
     assert spread["shift"] > 0.5, spread
     assert spread["guo"] < 0.1 * s0, (spread, s0)
+
+
+def test_shift_demixing_needs_small_tau(oracle_lib):
+    """Under the shift the force-driven flux carries tau and the pressure
+    flux tau - 1/2, so the demixing drive weakens as tau grows: at the
+    Fig. 2 couplings the mixture demixes at tau = 1.5 and relaxes at
+    tau = 2 (the threshold lies between 1.8 and 1.9); under Guo forcing it
+    relaxes even at tau = 0.8."""
+    n = 48
+    rho = inputs.random_densities(n, n, 1)
+    s0 = (rho[0] - rho[1]).std()
+
+    def spread(tau, forcing):
+        p = oracle_lib.Params(nx=n, ny=n, tau=(tau, tau), forcing=forcing, **BJ)
+        f = oracle_lib.init(p, rho)
+        oracle_lib.run(p, f, 2000)
+        r, _, _ = oracle_lib.moments(p, f)
+        return (r[0] - r[1]).std() / s0
+
+    assert spread(1.5, "shift") > 5.0
+    assert spread(2.0, "shift") < 0.1
+    assert spread(0.8, "guo") < 0.1

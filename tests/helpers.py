@@ -93,3 +93,26 @@ def oracle_window_moments(nx, ny, seed, sites, steps, mean=(0.7, 0.7), amp=0.05,
         r, ux, uy = oracle.moments(p, f)
         out.append((r[0][h, h], r[1][h, h], ux[h, h], uy[h, h]))
     return np.array(out)
+
+
+def oracle_column_moments(nx, ny, seed, columns, steps, boundary="walls", mean=(0.7, 0.7),
+                          amp=0.05, **kw):
+    """Oracle (rho_A, rho_B, u_x, u_y) of whole columns x in `columns` of the
+    nx x ny lattice (walls or periodic in y) started from
+    inputs.random_densities(nx, ny, seed), after `steps` steps, each from a
+    full-height window periodic in x around the column (exact for the
+    centre column by the same reach argument as the square windows).
+    Returns an array [len(columns), 4, ny]."""
+    okw = {k: v for k, v in kw.items() if k in _ORACLE_KEYS}
+    h = window_half_width(steps)
+    w = 2 * h + 1
+    p = oracle.Params(nx=w, ny=ny, walls=(boundary == "walls"), **okw)
+    out = []
+    for x in columns:
+        xs = np.arange(x - h, x + h + 1) % nx
+        rho = inputs.random_densities_window(nx, ny, seed, np.arange(ny), xs, mean, amp)
+        f = oracle.init(p, rho)
+        oracle.run(p, f, steps)
+        r, ux, uy = oracle.moments(p, f)
+        out.append(np.stack([r[0][:, h], r[1][:, h], ux[:, h], uy[:, h]]))
+    return np.array(out)

@@ -156,3 +156,36 @@ def test_largest_lattices_sampled(storage, n, tol):
     print(f"  tiling {tl}, {len(sites)} sites: max |drho| {e_rho:.3g}, |du| {e_u:.3g}", flush=True)
     assert bad == 0
     assert e_rho <= tol and e_u <= tol, (e_rho, e_u)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 20 * 1e-6), ("f16dev", 20 * 1.5e-4)])
+def test_sheared_cell_columns(storage, tol):
+    """The 1024x1024 sheared cell (top wall at U = 0.1) in the benchmark's
+    launch configuration, 20 steps: whole columns on strip edges and at the
+    lattice edges, wall rows included, against the oracle run on full-height
+    windows.  Bound: the one-step bound accumulated over 20 steps."""
+    import torch
+    from helpers import oracle_column_moments
+    from paper_0807_4471_amd import sclbm
+    n, seed, steps = 1024, 13, 20
+    kw = dict(WORKLOAD, wall_u=(0.0, 0.1))
+    banner(f"{storage} {n}x{n} sheared cell, {steps} steps, column windows")
+    sim = sclbm.Simulation(n, n, storage=storage, boundary="walls", tiling="auto",
+                           rho_ref=(0.7, 0.7), **kw)
+    sim.init_random(seed)
+    sim.step(steps)
+    W = sim.get_tiling()[0]
+    cols = sorted({0, 1, W - 1, W, 2 * W - 1, 2 * W, n // 2, n - 1})
+    m = sim.moments_device()
+    ix = torch.tensor(cols, device=m["rhoA"].device)
+    got = np.stack([np.stack([m[k][:, ix].cpu().numpy().T[j] for k in ("rhoA", "rhoB", "ux",
+                                                                     "uy")])
+                    for j in range(len(cols))])
+    sim.close()
+    ref = oracle_column_moments(n, n, seed, cols, steps, boundary="walls", **kw)
+    e_rho = float(np.abs(got[:, :2] - ref[:, :2]).max())
+    e_u = float(np.abs(got[:, 2:] - ref[:, 2:]).max())
+    e_wall = float(np.abs(got[:, :2, [0, -1]] - ref[:, :2, [0, -1]]).max())
+    print(f"  columns {cols}: max |drho| {e_rho:.3g} (wall rows {e_wall:.3g}), |du| {e_u:.3g}",
+          flush=True)
+    assert e_rho <= tol and e_u <= tol, (e_rho, e_u)

@@ -45,3 +45,17 @@ def test_too_narrow_window_differs():
     finally:
         helpers.window_half_width = orig
     assert not np.array_equal(narrow, ref)
+
+
+def test_column_window_with_walls_reproduces_full_lattice_bitwise():
+    """Full-height windows, periodic in x, with the moving walls: the centre
+    column equals the full lattice's, wall rows included."""
+    from helpers import oracle_column_moments
+    nx, ny, seed, steps = 41, 12, 8, 2
+    kw = dict(WORKLOAD, wall_u=(0.01, -0.04))
+    cols = [0, 20, 40]
+    got = oracle_column_moments(nx, ny, seed, cols, steps, boundary="walls", **kw)
+    _, _, (r, ux, uy) = oracle_run(nx, ny, steps, seed=seed, boundary="walls", **kw)
+    for k, x in enumerate(cols):
+        ref = np.stack([r[0][:, x], r[1][:, x], ux[:, x], uy[:, x]])
+        assert np.array_equal(got[k], ref), x

@@ -13,7 +13,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsclbm.so")
-SOURCES = ["sclbm_kernels.hip", "sclbm_api.cpp"]
+# (source, extra flags, object name): the kernel file is compiled once per
+# storage type so the four kernel sets build in parallel.
+UNITS = [("sclbm_kernels.hip", ["-DSCLBM_STORAGE=%d" % k], "sclbm_kernels_s%d.o" % k)
+         for k in range(4)] + [("sclbm_dispatch.cpp", [], "sclbm_dispatch.o"),
+                               ("sclbm_api.cpp", [], "sclbm_api.o")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -53,18 +57,31 @@ def kernel_source_hash() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
     t0 = time.time()
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, src + ".o")
+    cmds, objs = [], []
+    for src, extra, oname in UNITS:
+        obj = os.path.join(bdir, oname)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([HIPCC, *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    if verbose:
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        procs = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+    for c, p in zip(cmds, procs):
+        if p.returncode != 0:
+            sys.stderr.write(p.stdout + p.stderr)
+            raise subprocess.CalledProcessError(p.returncode, c)
+        if verbose and p.stderr.strip():
+            # hipcc's host pass does not know the packed-fp32 feature: harmless
+            lines = [ln for ln in p.stderr.splitlines() if "packed-fp32-ops" not in ln]
+            if lines:
+                print("\n".join(lines), flush=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -117,7 +117,7 @@ __host__ __device__ inline int fold_row(int r, int ny, bool walls)
     return r < ny ? r : p - 1 - r;
 }
 
-// Host-side launchers (defined in sclbm_kernels.hip).
+// Host-side launchers, dispatching on the storage type (sclbm_dispatch.cpp).
 // cw > 0: sweep strips cw waves wide; cw < 0: stacked tiles of -cw waves,
 // with write-through population stores if wt.
 hipError_t launch_sweep(int storage, int cw, int wt, int mode, const void* inst, int nblocks,
@@ -141,5 +141,28 @@ hipError_t launch_batch_step(int storage, int kind, const void* insts, const Bat
 hipError_t launch_init(int storage, const void* inst, const double* rhoA, const double* rhoB,
                        const double* ux, const double* uy, int random, uint64_t seed,
                        double meanA, double meanB, double amp, hipStream_t st);
+
+// The kernels of one storage type, from the unit built with -DSCLBM_STORAGE=k
+// (sclbm_kernels.hip is compiled once per storage type).
+#define SCLBM_CAT2_(a, b) a##b
+#define SCLBM_CAT_(a, b) SCLBM_CAT2_(a, b)
+#define SCLBM_SFX(name) SCLBM_CAT_(name, SCLBM_CAT_(_s, SCLBM_STORAGE))
+#define SCLBM_DECLARE_STORAGE_UNIT(k)                                                       \
+    hipError_t launch_sweep_s##k(int cw, int wt, int walls, int mode, const void* inst,   \
+                                 int nb, hipStream_t st);                                 \
+    int batch_grid_s##k(int kind);                                                        \
+    hipError_t launch_batch_s##k(int kind, const void* insts, const BatchItem* items,     \
+                                 int nitems, int64_t max_steps, BatchCtl* ctl,             \
+                                 uint32_t spin_limit, int grid, hipStream_t st);          \
+    hipError_t launch_batch_step_s##k(int kind, const void* insts, const BatchItem* items, \
+                                      int nitems, int64_t s, hipStream_t st);             \
+    hipError_t launch_init_s##k(const void* inst, const double* rA, const double* rB,     \
+                                const double* ux, const double* uy, int random,           \
+                                uint64_t seed, double mA, double mB, double amp,          \
+                                hipStream_t st);
+SCLBM_DECLARE_STORAGE_UNIT(0)
+SCLBM_DECLARE_STORAGE_UNIT(1)
+SCLBM_DECLARE_STORAGE_UNIT(2)
+SCLBM_DECLARE_STORAGE_UNIT(3)
 
 }  // namespace sclbm

@@ -732,6 +732,7 @@ __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typen
         block_reduce<RW>(acc, red, I.partials + (int64_t)b * NDIAG);
 }
 
+#if SCLBM_STORAGE == 0
 // Fixed-order FP64 reduction of per-block partials: deterministic.
 __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ partials, int nb,
                                                      double* __restrict__ out)
@@ -751,6 +752,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
         __syncthreads();
     }
 }
+#endif
 
 // SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator: output
 // number c of the stream seeded with `seed`.
@@ -987,17 +989,6 @@ static int batch_grid_k(int kind)
     return 0;
 }
 
-int batch_grid(int storage, int kind)
-{
-    switch (storage) {
-    case 0: return batch_grid_k<TF64>(kind);
-    case 1: return batch_grid_k<TF32>(kind);
-    case 2: return batch_grid_k<TF16>(kind);
-    case 3: return batch_grid_k<TF16SR>(kind);
-    }
-    return 0;
-}
-
 template <class T, int KIND>
 static hipError_t batch_go(const void* insts, const BatchItem* items, int nitems,
                            int64_t max_steps, BatchCtl* ctl, uint32_t spin_limit, int grid,
@@ -1044,32 +1035,6 @@ static hipError_t batch_step_go(int kind, const void* insts, const BatchItem* it
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_batch_step(int storage, int kind, const void* insts, const BatchItem* items,
-                             int nitems, int64_t s, hipStream_t st)
-{
-    switch (storage) {
-    case 0: return batch_step_go<TF64>(kind, insts, items, nitems, s, st);
-    case 1: return batch_step_go<TF32>(kind, insts, items, nitems, s, st);
-    case 2: return batch_step_go<TF16>(kind, insts, items, nitems, s, st);
-    case 3: return batch_step_go<TF16SR>(kind, insts, items, nitems, s, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_batch(int storage, int kind, const void* insts, const BatchItem* items,
-                        int nitems, int64_t max_steps, BatchCtl* ctl, uint32_t spin_limit,
-                        int grid, hipStream_t st)
-{
-    const uint32_t L = spin_limit;
-    switch (storage) {
-    case 0: return batch_go_k<TF64>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
-    case 1: return batch_go_k<TF32>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
-    case 2: return batch_go_k<TF16>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
-    case 3: return batch_go_k<TF16SR>(kind, insts, items, nitems, max_steps, ctl, L, grid, st);
-    }
-    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1140,26 +1105,6 @@ static hipError_t go_cw(int cw, int wt, int walls, int mode, const void* inst, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep(int storage, int cw, int wt, int mode, const void* inst, int nb,
-                        hipStream_t st)
-{
-    // walls flag lives in the Geo at the same offset for every instantiation
-    const int walls = static_cast<const Inst<float, float>*>(inst)->g.walls;
-    switch (storage) {
-    case 0: return go_cw<TF64>(cw, wt, walls, mode, inst, nb, st);
-    case 1: return go_cw<TF32>(cw, wt, walls, mode, inst, nb, st);
-    case 2: return go_cw<TF16>(cw, wt, walls, mode, inst, nb, st);
-    case 3: return go_cw<TF16SR>(cw, wt, walls, mode, inst, nb, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_reduce(const double* partials, int nb, double* out, hipStream_t st)
-{
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, partials, nb, out);
-    return hipGetLastError();
-}
-
 template <class T>
 static hipError_t init_go(const void* inst, const double* rA, const double* rB,
                           const double* ux, const double* uy, int random, uint64_t seed,
@@ -1173,17 +1118,58 @@ static hipError_t init_go(const void* inst, const double* rA, const double* rB,
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, const void* inst, const double* rA, const double* rB,
-                       const double* ux, const double* uy, int random, uint64_t seed,
-                       double mA, double mB, double amp, hipStream_t st)
+// ------------------------------------------------- entry points of this unit
+//
+// The file is compiled once per storage type (-DSCLBM_STORAGE = 0 FP64, 1
+// FP32, 2 FP16 deviations, 3 FP16 deviations with stochastic rounding), so
+// the four sets of kernels build in parallel; the storage-dispatching
+// launchers of sclbm_internal.h call the suffixed functions below.
+#if SCLBM_STORAGE == 0
+using TS = TF64;
+#elif SCLBM_STORAGE == 1
+using TS = TF32;
+#elif SCLBM_STORAGE == 2
+using TS = TF16;
+#elif SCLBM_STORAGE == 3
+using TS = TF16SR;
+#else
+#error "SCLBM_STORAGE must be 0, 1, 2 or 3"
+#endif
+
+hipError_t SCLBM_SFX(launch_sweep)(int cw, int wt, int walls, int mode, const void* inst, int nb,
+                                   hipStream_t st)
 {
-    switch (storage) {
-    case 0: return init_go<TF64>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
-    case 1: return init_go<TF32>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
-    case 2: return init_go<TF16>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
-    case 3: return init_go<TF16SR>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
-    }
-    return hipErrorInvalidValue;
+    return go_cw<TS>(cw, wt, walls, mode, inst, nb, st);
 }
+
+int SCLBM_SFX(batch_grid)(int kind) { return batch_grid_k<TS>(kind); }
+
+hipError_t SCLBM_SFX(launch_batch)(int kind, const void* insts, const BatchItem* items,
+                                   int nitems, int64_t max_steps, BatchCtl* ctl,
+                                   uint32_t spin_limit, int grid, hipStream_t st)
+{
+    return batch_go_k<TS>(kind, insts, items, nitems, max_steps, ctl, spin_limit, grid, st);
+}
+
+hipError_t SCLBM_SFX(launch_batch_step)(int kind, const void* insts, const BatchItem* items,
+                                        int nitems, int64_t s, hipStream_t st)
+{
+    return batch_step_go<TS>(kind, insts, items, nitems, s, st);
+}
+
+hipError_t SCLBM_SFX(launch_init)(const void* inst, const double* rA, const double* rB,
+                                  const double* ux, const double* uy, int random, uint64_t seed,
+                                  double mA, double mB, double amp, hipStream_t st)
+{
+    return init_go<TS>(inst, rA, rB, ux, uy, random, seed, mA, mB, amp, st);
+}
+
+#if SCLBM_STORAGE == 0
+hipError_t launch_reduce(const double* partials, int nb, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+#endif
 
 }  // namespace sclbm

@@ -24,7 +24,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sclbm_oracle.c")
 _LIB = os.path.join(_HERE, "libsclbm_oracle.so")
 
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99"]
+# -fopenmp: rows of a step run in parallel (same arithmetic for any thread count)
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99",
+          "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -105,6 +107,10 @@ def lib():
         L.oracle_totals.argtypes = [pp, dp, dp]
         L.oracle_row_profiles.argtypes = [pp, dp, dp, dp]
         L.oracle_shear_flow.argtypes = [pp, dp, dp]
+        L.oracle_set_threads.argtypes = [ctypes.c_int32]
+        L.oracle_set_threads.restype = ctypes.c_int32
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = ctypes.c_int32
         for name in ("oracle_forces", "oracle_init", "oracle_run", "oracle_moments",
                      "oracle_totals", "oracle_row_profiles", "oracle_shear_flow"):
             getattr(L, name).restype = ctypes.c_int32
@@ -122,6 +128,16 @@ def _ptr(a):
 def _check(rc, what):
     if rc != 0:
         raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's row loops (n < 1: all processors); returns the
+    number set.  Results do not depend on it."""
+    return int(lib().oracle_set_threads(int(n)))
+
+
+def threads() -> int:
+    return int(lib().oracle_threads())
 
 
 def d2q9():

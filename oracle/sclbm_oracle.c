@@ -49,6 +49,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define CS2 (1.0 / 3.0)
 
@@ -113,6 +116,27 @@ void oracle_stencil(int32_t ex[24], int32_t ey[24], double wa[24], double wr[24]
     if (p0) *p0 = 247.0 / 420.0;
 }
 
+int32_t oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n < 1) n = omp_get_num_procs();
+    omp_set_num_threads(n);
+    return n;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+int32_t oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 double oracle_psi(const oracle_params* p, double rho)
 {
     return p->psi_amp * (1.0 - exp(-rho / p->rho0));
@@ -166,6 +190,7 @@ int32_t oracle_forces(const oracle_params* p, const double* psi, const double* r
         const double* ps = psi + s * N;
         const double* rs = rho + s * N;
         const double* ro = rho + so * N;
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) {
             for (int x = 0; x < nx; ++x) {
                 const size_t n = (size_t)y * nx + x;
@@ -208,9 +233,9 @@ int32_t oracle_init(const oracle_params* p, const double* rho, const double* ux,
 {
     if (!valid(p)) return -1;
     const size_t N = (size_t)p->nx * p->ny;
-    double feq[9];
     for (int s = 0; s < 2; ++s)
         for (size_t n = 0; n < N; ++n) {
+            double feq[9];
             oracle_feq(rho[s * N + n], ux ? ux[n] : 0.0, uy ? uy[n] : 0.0, feq);
             for (int i = 0; i < 9; ++i) f[(s * 9 + i) * N + n] = feq[i];
         }
@@ -225,6 +250,7 @@ static void fields(const oracle_params* p, const double* f, double* rho, double*
     const int nx = p->nx, ny = p->ny;
     const size_t N = (size_t)nx * ny;
     for (int s = 0; s < 2; ++s)
+#pragma omp parallel for schedule(static)
         for (size_t n = 0; n < N; ++n) {
             double r = 0.0, mx = 0.0, my = 0.0;
             for (int i = 0; i < 9; ++i) {
@@ -241,6 +267,7 @@ static void fields(const oracle_params* p, const double* f, double* rho, double*
     oracle_forces(p, psi, rho, F);
     if (p->body_F0 != 0.0) {
         const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) {
             const double sy = sin(two_pi * (double)y / (double)ny);
             for (int x = 0; x < nx; ++x) {
@@ -267,12 +294,17 @@ int32_t oracle_run(const oracle_params* p, double* f, int64_t nsteps, double* wa
         free(rho); free(jx); free(jy); free(psi); free(F); free(fn);
         return -2;
     }
-    double feq[9];
     for (int64_t t = 0; t < nsteps; ++t) {
         fields(p, f, rho, jx, jy, psi, F);
+        /* Rows run in parallel: every site writes its own streamed
+         * destinations, and only row 0 (bottom wall) and row ny - 1 (top
+         * wall) add into wall_mom, each into its own entries in site order,
+         * so the result is the same for any number of threads. */
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 const size_t n = (size_t)y * nx + x;
+                double feq[9];
                 double upx = 0.0, upy = 0.0;
                 if (p->forcing == 0) {
                     /* Common velocity u' weighted by rho_s / tau_s. */
@@ -358,8 +390,9 @@ static int observe(const oracle_params* p, const double* f, double* rho, double*
         return -2;
     }
     fields(p, f, r, jx, jy, psi, F);
-    double feq[9];
+#pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; ++n) {
+        double feq[9];
         double mx = 0.0, my = 0.0, rt = 0.0;
         for (int s = 0; s < 2; ++s) {
             mx += jx[s * N + n] + 0.5 * F[(s * 2 + 0) * N + n];

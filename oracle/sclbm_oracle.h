@@ -108,6 +108,13 @@ int32_t oracle_row_profiles(const oracle_params* p, const double* f, double* ux_
  *           (neighbours wrapped, or mirrored at walls)                      */
 int32_t oracle_shear_flow(const oracle_params* p, const double* f, double out[2]);
 
+/* Threads of the oracle's parallel loops (OpenMP over lattice rows; the
+ * arithmetic, and so every result, is the same for any number of threads).
+ * n < 1 selects all processors.  Returns the number set (1 without OpenMP). */
+int32_t oracle_set_threads(int32_t n);
+/* Threads the next parallel loop will use. */
+int32_t oracle_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

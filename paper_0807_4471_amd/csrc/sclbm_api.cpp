@@ -741,6 +741,12 @@ int32_t batch_layout(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tl
                  ((h->d.ny + tl[k].tile_y - 1) / tl[k].tile_y);
     }
     if (items > (1 << 30)) return fail(SCLBM_ESIZE, "too many tiles");
+    // one state stepped twice in one launch would race, and its time and
+    // ping-pong copy would be advanced twice
+    std::vector<const sclbm_inst*> seen(insts, insts + n);
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        return fail(SCLBM_EINVAL, "the same instance appears twice in a batch");
     *inst_bytes = align_up(batch_inst_size(storage) * n, ALIGN);
     *off_items = *inst_bytes;
     *off_ctl = *off_items + align_up(sizeof(BatchItem) * (size_t)items, ALIGN);

@@ -83,3 +83,17 @@ def droplet_densities(nx: int, ny: int, radius: float, rho_in: float, rho_out: f
     rho[0] = rho_out + (rho_in - rho_out) * s
     rho[1] = rho_in + (rho_out - rho_in) * s
     return rho
+
+
+def batch_mix(seed: int = 2026, n: int = 64) -> list[dict]:
+    """Parameters of the uneven batch workload: n instances with sides from
+    {128, 192, 256, 384, 512}, rho0 ~ U(0.60, 0.80), G^X ~ U(0.50, 0.65),
+    tau_s ~ U(0.8, 1.2) per species (numpy generator `seed`), instance i
+    initialised by random_densities(..., seed=1000 + i)."""
+    rng = np.random.default_rng(seed)
+    sides = rng.choice([128, 192, 256, 384, 512], size=n)
+    rho0 = rng.uniform(0.60, 0.80, n)
+    gx = rng.uniform(0.50, 0.65, n)
+    tau = rng.uniform(0.8, 1.2, (n, 2))
+    return [dict(nx=int(sides[i]), ny=int(sides[i]), rho0=float(rho0[i]), Gx=float(gx[i]),
+                 tau=(float(tau[i, 0]), float(tau[i, 1])), seed=1000 + i) for i in range(n)]

@@ -59,7 +59,8 @@ class Result:
     arrival: float
     admitted: float
     finished: float
-    status: str               # "ok" or "failed"
+    status: str               # "ok", "failed" (non-finite state) or "rejected"
+                              # (footprint above the server's HBM budget)
     moments: dict | None
     diag: dict | None
 
@@ -128,6 +129,12 @@ class Server:
                  slicing: str = "steps"):
         if slicing not in ("work", "steps"):
             raise ValueError("slicing must be 'work' or 'steps'")
+        if int(hbm_budget) <= 0:
+            raise ValueError("hbm_budget must be > 0 bytes")
+        if int(max_slots) < 1:
+            raise ValueError("max_slots must be >= 1")
+        if not float(chunk_ms) > 0.0:
+            raise ValueError("chunk_ms must be > 0")
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.chunk_ms = float(chunk_ms)
@@ -170,6 +177,15 @@ class Server:
             while pi < len(pending) and pending[pi].arrival <= now:
                 req = pending[pi]
                 need = footprint(req)
+                if need > self.budget:
+                    # can never fit, even alone: refuse it now instead of
+                    # holding the queue (and everything behind it) forever
+                    results[req.rid] = Result(req.rid, req.arrival, now, now, "rejected",
+                                              None, None)
+                    pi += 1
+                    if on_event:
+                        on_event("reject", req.rid, now)
+                    continue
                 if len(active) >= self.max_slots or used + need > self.budget:
                     break
                 sim = _new_sim(req, self.device)
@@ -181,6 +197,8 @@ class Server:
                 if on_event:
                     on_event("admit", req.rid, now)
             if not active:
+                if pi >= len(pending):
+                    break  # everything left was rejected
                 # idle until the next arrival
                 wait = pending[pi].arrival - (time.perf_counter() - t0)
                 if wait > 0:
@@ -285,11 +303,15 @@ def summarize_public(s: dict) -> dict:
 
 
 def summarize(trace, results: dict, makespan: float, busy: float) -> dict:
-    lat = np.array([results[r.rid].latency for r in trace if r.rid in results])
-    work = sum(r.work for r in trace if r.rid in results)
-    failed = sum(1 for r in results.values() if r.status != "ok")
+    """Latency percentiles and throughput over the requests that ran (ok or
+    failed); rejected requests are counted apart."""
+    ran = [r for r in trace if r.rid in results and results[r.rid].status != "rejected"]
+    lat = np.array([results[r.rid].latency for r in ran])
+    work = sum(r.work for r in ran)
+    failed = sum(1 for r in results.values() if r.status == "failed")
+    rejected = sum(1 for r in results.values() if r.status == "rejected")
     return {
-        "requests": len(trace), "completed": len(results), "failed": failed,
+        "requests": len(trace), "completed": len(ran), "failed": failed, "rejected": rejected,
         "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
         "mean_latency_s": float(lat.mean()) if len(lat) else None,

@@ -116,3 +116,46 @@ def oracle_column_moments(nx, ny, seed, columns, steps, boundary="walls", mean=(
         r, ux, uy = oracle.moments(p, f)
         out.append(np.stack([r[0][:, h], r[1][:, h], ux[:, h], uy[:, h]]))
     return np.array(out)
+
+
+# One-step rounding bounds of the stored densities (max |drho| after one
+# step against the FP64 oracle), derived from the storage arithmetic: a
+# density is a sum of 9 stored populations, FP32 rounds values <= 0.5 to
+# <= 2^-25 each (9 * 2^-25 ~ 3e-7, plus the FP32 collision of the same
+# order); binary16 deviations |h| <= ~0.03 have ulp 2^-16, so <= 9 * 2^-17 ~
+# 7e-5 per step.  Rounded up to 1e-6 and 1.5e-4.
+ONE_STEP = {"f32": 1e-6, "f16dev": 1.5e-4, "f16sr": 1.5e-4}
+
+
+def oracle_amplification(nx, ny, steps, seed=1, rho=None, boundary="periodic", eps=1e-9, **kw):
+    """Envelope A(m), m = 0..steps, of the growth of a small density
+    perturbation over m steps of this case, measured on the oracle: the
+    initial densities are perturbed by at most eps (a seeded +-pattern), both
+    runs advance step by step, and A(m) is the largest ratio max|drho(k)| /
+    max|drho(0)| for k <= m (so it is non-decreasing, and >= 1)."""
+    okw = {k: v for k, v in kw.items() if k in _ORACLE_KEYS}
+    p = oracle.Params(nx=nx, ny=ny, walls=(boundary == "walls"), **okw)
+    if rho is None:
+        rho = inputs.random_densities(nx, ny, seed)
+    pert = eps * inputs.uniform_pm1(seed + 7919, np.arange(2 * nx * ny)).reshape(2, ny, nx)
+    f0 = oracle.init(p, rho)
+    f1 = oracle.init(p, rho + pert)
+    d0 = np.abs(oracle.moments(p, f1)[0] - oracle.moments(p, f0)[0]).max()
+    amp = np.ones(steps + 1)
+    for m in range(1, steps + 1):
+        oracle.run(p, f0, 1)
+        oracle.run(p, f1, 1)
+        d = np.abs(oracle.moments(p, f1)[0] - oracle.moments(p, f0)[0]).max()
+        amp[m] = max(amp[m - 1], d / d0)
+    return amp
+
+
+def accumulated_bound(storage, amp, steps):
+    """Bound on max |drho| after `steps` steps in reduced-precision storage:
+    the stored initial state and every step each add at most
+    ONE_STEP[storage], and an error made k steps before the end grows at
+    most by the envelope A(k) (oracle_amplification), so the sum is
+    ONE_STEP * sum_{k <= steps} A(k).  A factor 2 covers rounding of
+    populations that leaves the density unchanged (momentum, stress) and may
+    grow differently from a density perturbation."""
+    return 2.0 * ONE_STEP[storage] * float(np.sum(amp[:steps + 1]))

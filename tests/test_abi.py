@@ -148,3 +148,30 @@ def test_largest_square_lattice(L, storage, eb, largest):
     h = ctypes.c_void_p()
     rc = L.lib.sclbm_bind(ctypes.byref(d), ctypes.c_void_p(1 << 20), 1 << 40, ctypes.byref(h))
     assert rc == L.EUNSUPPORTED and not h.value
+
+
+def test_batch_rejects_a_repeated_instance(L):
+    """One state named twice in a batch would be stepped twice per launch
+    (racing) and have its time and ping-pong copy advanced twice: refused
+    before any device work."""
+    d = L.make_desc(64, 64, storage="f32")
+    need = L.state_bytes(d)
+    hs = [ctypes.c_void_p(), ctypes.c_void_p()]
+    for k, h in enumerate(hs):
+        fake = ctypes.c_void_p((1 << 30) * (k + 1))   # never dereferenced
+        assert L.lib.sclbm_bind(ctypes.byref(d), fake, need, ctypes.byref(h)) == L.OK
+    try:
+        tl = (L.Tiling * 2)(L.Tiling(60, 4, 4, 1), L.Tiling(60, 4, 4, 1))
+        two = (ctypes.c_void_p * 2)(hs[0].value, hs[1].value)
+        same = (ctypes.c_void_p * 2)(hs[0].value, hs[0].value)
+        assert L.lib.sclbm_batch_bytes(two, 2, tl) > 0
+        assert L.lib.sclbm_batch_bytes(same, 2, tl) == 0
+        assert "twice" in L.last_error()
+        out = ctypes.c_void_p()
+        ws = ctypes.c_void_p(1 << 34)
+        assert L.lib.sclbm_batch_plan(same, 2, tl, ws, 1 << 20, None,
+                                      ctypes.byref(out)) == L.EINVAL
+        assert out.value is None
+    finally:
+        for h in hs:
+            L.lib.sclbm_release(h)

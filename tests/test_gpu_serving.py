@@ -45,23 +45,30 @@ def test_results_equal_running_alone(slicing):
 
 
 def test_admission_respects_budget_and_slots():
+    """Budget and slot limits hold at every moment; a request larger than the
+    whole budget, arriving mid-trace, is rejected and holds up nothing."""
     from paper_0807_4471_amd import serving
-    banner("serving: HBM budget and slots")
+    banner("serving: HBM budget and slots, one request too large for the budget")
     trace = _trace()
     budget = 2 * max(serving.footprint(r) for r in trace)
+    big = serving.Request(rid=len(trace), arrival=trace[3].arrival, nx=1024, ny=1024, steps=10,
+                          seed=99)
+    assert serving.footprint(big) > budget
+    trace = trace + [big]
     live, peak_bytes, peak_n = {}, 0, 0
 
     def ev(kind, rid, t):
         nonlocal peak_bytes, peak_n
         if kind == "admit":
             live[rid] = serving.footprint(trace[rid])
-        else:
+        elif kind == "finish":
             live.pop(rid)
         peak_bytes = max(peak_bytes, sum(live.values()))
         peak_n = max(peak_n, len(live))
 
     out = serving.Server(hbm_budget=budget, max_slots=3, chunk_ms=0.5).run(trace, on_event=ev)
-    assert out["completed"] == len(trace)
+    assert out["completed"] == len(trace) - 1 and out["rejected"] == 1
+    assert out["results"][big.rid].status == "rejected"
     assert peak_bytes <= budget and peak_n <= 3
 
 
@@ -88,3 +95,35 @@ def test_corrupted_request_fails_alone():
         if req.rid != victim:
             ref = _alone(req)
             assert np.array_equal(out["results"][req.rid].moments["rhoA"], ref["rhoA"]), req.rid
+
+
+def test_served_results_match_oracle():
+    """Every request of a short overlapping trace (FP64, FP32 and FP16
+    storage; periodic and moving walls) served with continuous batching,
+    against the FP64 oracle run on the same request: FP64 to 1e-12, FP32 and
+    FP16 within the accumulated rounding bound of helpers.accumulated_bound
+    (one-step bound summed over the steps, amplified at most as the oracle
+    measures for a perturbation of the same request)."""
+    from helpers import WORKLOAD, accumulated_bound, max_err, oracle_amplification, oracle_run
+    from paper_0807_4471_amd import serving
+    banner("serving: served results vs FP64 oracle")
+    trace = serving.make_trace(9, rate=4000.0, seed=11, side=(24, 72), steps=(40, 160),
+                               storages=("f64", "f32", "f16dev"))
+    assert {r.storage for r in trace} == {"f64", "f32", "f16dev"}
+    assert {r.boundary for r in trace} == {"periodic", "walls"}
+    out = serving.Server(chunk_ms=0.3).run(trace)
+    assert out["completed"] == len(trace) and out["failed"] == 0
+    for req in trace:
+        kw = dict(WORKLOAD, wall_u=(0.0, req.wall_u))
+        _, _, ref = oracle_run(req.nx, req.ny, req.steps, seed=req.seed, boundary=req.boundary,
+                               **kw)
+        e = max_err(out["results"][req.rid].moments, ref)
+        if req.storage == "f64":
+            tol = 1e-12
+        else:
+            amp = oracle_amplification(req.nx, req.ny, req.steps, seed=req.seed,
+                                       boundary=req.boundary, **kw)
+            tol = accumulated_bound(req.storage, amp, req.steps)
+        print(f"  request {req.rid} {req.nx}^2 {req.storage} {req.boundary} U={req.wall_u} "
+              f"steps={req.steps}: err {e}, bound {tol:.3g}", flush=True)
+        assert e["rho"] <= tol and e["u"] <= tol, (req.rid, e, tol)

@@ -35,3 +35,21 @@ def test_summary_percentiles():
     assert abs(out["p50_latency_s"] - (1.0 + 0.01 * 49.5)) < 1e-9
     assert out["p99_latency_s"] > 1.98
     assert abs(out["aggregate_mlups"] - 100 * 100 * 100 / 200.0 / 1e6) < 1e-12
+
+
+def test_request_that_can_never_fit_is_rejected_not_waited_for():
+    """A request whose state exceeds the whole HBM budget is refused at
+    admission (status "rejected"); the loop does not wait for room that can
+    never appear.  Every request here is too large, so no device work runs."""
+    trace = serving.make_trace(5, rate=1e6, seed=3, side=(64, 128), steps=(10, 20))
+    out = serving.Server(hbm_budget=1024).run(trace)
+    assert out["rejected"] == 5 and out["completed"] == 0 and out["failed"] == 0
+    assert all(r.status == "rejected" and r.moments is None for r in out["results"].values())
+
+
+def test_server_parameters_are_validated():
+    import pytest
+    for bad in (dict(hbm_budget=0), dict(max_slots=0), dict(chunk_ms=0.0),
+                dict(slicing="fifo")):
+        with pytest.raises(ValueError):
+            serving.Server(**bad)

@@ -432,9 +432,11 @@ def run_batch(a, torch, sclbm):
     mix = batch_mix()
     sites = sum(m["nx"] * m["ny"] for m in mix)
 
-    def make(tiling=None):
+    def make(tiling=None, subset=None):
         sims = []
-        for m in mix:
+        for i, m in enumerate(mix):
+            if subset is not None and i not in subset:
+                continue
             kw = dict(WORKLOAD, rho0=m["rho0"], Gx=m["Gx"], tau=m["tau"])
             s = sclbm.Simulation(m["nx"], m["ny"], storage="f32", tiling=tiling, **kw)
             s.init_random(m["seed"])
@@ -460,10 +462,26 @@ def run_batch(a, torch, sclbm):
     ms_s, _ = timed(torch, lambda: [s.step(a.batch_steps) for s in seq])
     ms_s2, _ = timed(torch, lambda: [s.step(a.batch_steps) for s in seq])
     same = all(torch.equal(x.buf[:x.nbytes], y.buf[:y.nbytes]) for x, y in zip(sims, seq))
-    bad = sum(1 for s in sims if s.diagnostics()["bad_sites"] > 0)
+    # instances whose densities left the physical range (non-positive sites;
+    # the method under these readings with tau_s < 1, recorded by the oracle
+    # for the 128^2 members): reported apart, and the healthy ones timed again
+    # as a batch of their own
+    bad_sites = [s.diagnostics()["bad_sites"] for s in sims]
+    diverged = [i for i, b in enumerate(bad_sites) if b > 0]
+    healthy = [i for i, b in enumerate(bad_sites) if b == 0]
     for s in sims + seq:
         s.close()
     del sims, seq
+    torch.cuda.empty_cache()
+    hs = make(subset=healthy)
+    bh = sclbm.Batch(hs, "auto")
+    ms_h, _ = timed(torch, lambda: bh.step(a.batch_steps))
+    bh.status()
+    bh.close()
+    h_sites = sum(mix[i]["nx"] * mix[i]["ny"] for i in healthy)
+    for s in hs:
+        s.close()
+    del hs
     torch.cuda.empty_cache()
     lups = sites * a.batch_steps
     out = {"workload": "64 uneven FP32 instances (128^2..512^2, rho0~U(0.6,0.8), "
@@ -475,7 +493,15 @@ def run_batch(a, torch, sclbm):
            "sequential_mlups": round(2 * lups / ((ms_s + ms_s2) * 1e-3) / 1e6, 1),
            "speedup": round((ms_s + ms_s2) / 2 / ms_b, 3),
            "bitwise_equal_to_sequential": bool(same),
-           "instances_with_bad_sites": bad, "plan": info, "persistent_plan": info_p}
+           "instances_with_bad_sites": len(diverged),
+           "diverged": {"instances": diverged, "bad_sites": [bad_sites[i] for i in diverged],
+                        "share_of_sites": round(1.0 - h_sites / sites, 4),
+                        "note": "densities left the physical range (non-positive sites, "
+                                "guarded and counted by the kernels); every such instance "
+                                "has a tau_s < 1 (velocity-shift coupling)"},
+           "healthy": {"instances": len(healthy), "sites": h_sites,
+                       "batched_mlups": round(h_sites * a.batch_steps / (ms_h * 1e-3) / 1e6, 1)},
+           "plan": info, "persistent_plan": info_p}
     log(f"batch: {out}")
     return out
 

@@ -123,16 +123,22 @@ def oracle_column_moments(nx, ny, seed, columns, steps, boundary="walls", mean=(
 # density is a sum of 9 stored populations, FP32 rounds values <= 0.5 to
 # <= 2^-25 each (9 * 2^-25 ~ 3e-7, plus the FP32 collision of the same
 # order); binary16 deviations |h| <= ~0.03 have ulp 2^-16, so <= 9 * 2^-17 ~
-# 7e-5 per step.  Rounded up to 1e-6 and 1.5e-4.
-ONE_STEP = {"f32": 1e-6, "f16dev": 1.5e-4, "f16sr": 1.5e-4}
+# 7e-5 per step.  Rounded up to 1e-6 and 1.5e-4.  FP64: the same sum in
+# binary64 (9 * 2^-54 ~ 5e-16) plus a few hundred operations of the step,
+# each rounded to 2^-53 relative on values of order one, taken in a
+# different order (and with fused multiply-adds) on the GPU: 1e-14.
+ONE_STEP = {"f64": 1e-14, "f32": 1e-6, "f16dev": 1.5e-4, "f16sr": 1.5e-4}
 
 
-def oracle_amplification(nx, ny, steps, seed=1, rho=None, boundary="periodic", eps=1e-9, **kw):
+def oracle_amplification(nx, ny, steps, seed=1, rho=None, boundary="periodic", eps=1e-9,
+                         with_moments=False, **kw):
     """Envelope A(m), m = 0..steps, of the growth of a small density
     perturbation over m steps of this case, measured on the oracle: the
     initial densities are perturbed by at most eps (a seeded +-pattern), both
     runs advance step by step, and A(m) is the largest ratio max|drho(k)| /
-    max|drho(0)| for k <= m (so it is non-decreasing, and >= 1)."""
+    max|drho(0)| for k <= m (so it is non-decreasing, and >= 1).  With
+    with_moments, also returns the unperturbed run's final moments (those of
+    oracle_run on the same case)."""
     okw = {k: v for k, v in kw.items() if k in _ORACLE_KEYS}
     p = oracle.Params(nx=nx, ny=ny, walls=(boundary == "walls"), **okw)
     if rho is None:
@@ -147,6 +153,8 @@ def oracle_amplification(nx, ny, steps, seed=1, rho=None, boundary="periodic", e
         oracle.run(p, f1, 1)
         d = np.abs(oracle.moments(p, f1)[0] - oracle.moments(p, f0)[0]).max()
         amp[m] = max(amp[m - 1], d / d0)
+    if with_moments:
+        return amp, oracle.moments(p, f0)
     return amp
 
 

@@ -9,7 +9,7 @@ import os
 import numpy as np
 import pytest
 
-from helpers import WORKLOAD, banner, oracle_run
+from helpers import WORKLOAD, accumulated_bound, banner, oracle_amplification
 
 pytestmark = pytest.mark.gpu
 
@@ -44,29 +44,30 @@ def test_f64_batch_flags_the_oracle_instances_and_matches_it(mode):
     for r, s in zip(rows, sims):
         bad = s.diagnostics()["bad_sites"]
         m = mix[r["instance"]]
-        _, _, ref = oracle_run(m["nx"], m["ny"], steps, seed=m["seed"],
-                               **{**WORKLOAD, "rho0": m["rho0"], "Gx": m["Gx"], "tau": m["tau"]})
+        amp, ref = oracle_amplification(
+            m["nx"], m["ny"], steps, seed=m["seed"], with_moments=True,
+            **{**WORKLOAD, "rho0": m["rho0"], "Gx": m["Gx"], "tau": m["tau"]})
+        tol = accumulated_bound("f64", amp, steps)
         got = s.moments()
         err = max(np.abs(got["rhoA"] - ref[0][0]).max(), np.abs(got["rhoB"] - ref[0][1]).max())
         print(f"  instance {r['instance']}: bad {bad} (oracle {r['bad_sites']}), "
-              f"max|drho| {err:.3g}", flush=True)
+              f"max|drho| {err:.3g}, bound {tol:.3g} (growth {amp[-1]:.3g})", flush=True)
         assert bad == r["bad_sites"], r
-        assert err <= 1e-10, (r["instance"], err)
+        assert err <= tol, (r["instance"], err, tol)
 
 
-def test_f32_batch_flags_the_oracle_instances():
-    """The benchmark's storage: FP32 flags the same instances.  Instances the
-    oracle finds with only a handful of slightly negative sites (min rho >
-    -0.002) sit at the threshold, where FP32 rounding may tip a site either
-    way: for those only the magnitude is checked."""
-    banner("f32 stepwise batch of the 13 128^2 mix instances, 500 steps")
-    rows, _, sims, _ = _batch("f32", "stepwise")
+@pytest.mark.parametrize("mode", ["stepwise", "persistent"])
+def test_f32_batch_flags_the_oracle_instances(mode):
+    """The benchmark's storage: FP32 flags exactly the instances the oracle
+    flags.  Site counts may differ by a few where FP32 rounding tips a site
+    near rho = 0 either way: within 1% + 3 sites."""
+    banner(f"f32 {mode} batch of the 13 128^2 mix instances, 500 steps")
+    rows, _, sims, _ = _batch("f32", mode)
+    got = {}
     for r, s in zip(rows, sims):
         bad = s.diagnostics()["bad_sites"]
+        got[r["instance"]] = bad
         print(f"  instance {r['instance']}: bad {bad} (oracle {r['bad_sites']})", flush=True)
-        if r["bad_sites"] == 0 and r["min_rho"] > 0.01:
-            assert bad == 0, r
-        elif r["min_rho"] < -0.002:
-            assert abs(bad - r["bad_sites"]) <= 0.02 * r["bad_sites"] + 2, (bad, r)
-        else:
-            assert bad <= 20, (bad, r)
+        assert abs(bad - r["bad_sites"]) <= 0.01 * r["bad_sites"] + 3, (bad, r)
+    assert {i for i, b in got.items() if b > 0} == {r["instance"] for r in rows
+                                                    if r["bad_sites"] > 0}

@@ -5,10 +5,12 @@ The evaluator shares nothing with the oracle but the readings of the paper
 (leading minus sign of the forces, velocity-shift forcing, second-order
 equilibrium, half-way bounce-back with mirrored ghost rows).  It differs
 from the oracle wherever a mistake could hide:
-  * forces are unpaired sums over all 24 offsets e of K(|e|^2) e Psi(x + e)
-    (the oracle pairs e with -e and differences Psi), with K built from
-    weights solved exactly from the paper's constraints (not the oracle's
-    tables);
+  * forces are sums over all 24 offsets e of K(|e|^2) e Psi(x + e) with the
+    couplings folded into one kernel K = G^a w + G^r p, built from weights
+    solved exactly from the paper's constraints (not the oracle's tables);
+    the oracle also sums every offset on its own (no pairing of e with -e),
+    but keeps separate sums for the attractive, repulsive and cross terms
+    and multiplies by the couplings afterwards, in a different order;
   * neighbours come from np.roll / np.pad of whole fields (the oracle wraps
     indices per site);
   * streaming pushes whole planes with np.roll (the oracle loops over

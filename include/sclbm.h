@@ -316,6 +316,31 @@ int32_t sclbm_batch_info(const sclbm_batch* batch, int32_t out[3]);
 /* Free the batch handle (not the workspace or the instances). */
 int32_t sclbm_batch_release(sclbm_batch* batch);
 
+/* Bytes of the static device array behind sclbm_batch_step_static. */
+#define SCLBM_STATIC_SCRATCH_BYTES (4u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): plan and run
+ * a batch in one call, as sclbm_batch_plan + sclbm_batch_step in STEPWISE
+ * mode would, with the batch tables (per-instance parameters and tile
+ * table) in a static device array of SCLBM_STATIC_SCRATCH_BYTES instead of
+ * a caller workspace.  The library holds that array on every GPU it runs
+ * this call on until the process ends; its address on the current device is
+ * looked up once per device.  Arguments as for sclbm_batch_plan (insts,
+ * n >= 1, tiling) and sclbm_batch_step (steps[k] >= 0).  ESIZE, before any
+ * device work, if the tables exceed SCLBM_STATIC_SCRATCH_BYTES (each
+ * instance takes a parameter record of a few hundred bytes, each tile 8
+ * bytes: e.g. 64 instances of up to 500 000 tiles in all).
+ * Calls no allocation routine: the tables are built in a static host array,
+ * copied by one upload, and hip_stream (which must belong to the current
+ * device) is synced once after that upload; the step launches are then
+ * enqueued asynchronously.  Every call on a GPU shares that GPU's array and
+ * overwrites it, so calls whose work overlaps on one GPU (other streams,
+ * other host threads) race; host calls are serialised by a lock.  Results
+ * are bitwise those of sclbm_batch_step. */
+int32_t sclbm_batch_step_static(sclbm_inst* const* insts, int32_t n, const sclbm_tiling* tiling,
+                                const int64_t* steps, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -935,3 +936,107 @@ int32_t sclbm_batch_release(sclbm_batch* b)
 }
 
 }  // extern "C"
+
+// ----------------------------------------------- allocation-free batch step
+//
+// The tables of sclbm_batch_step_static live in this static device array
+// (one copy per GPU, held until the process ends).  In host code `scratch`
+// names a host-side stand-in, not the device array: its device address is
+// looked up with hipGetSymbolAddress once per device and only that address
+// is passed to kernels or copies.
+static __device__ __align__(256) char scratch[SCLBM_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;                       // guards the two arrays below
+char* g_scratch_dev[MAX_DEVICES] = {};        // device address of `scratch`, per device
+alignas(256) char g_stage[SCLBM_STATIC_SCRATCH_BYTES];  // host staging of the tables
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on that device).  Called with g_static_mu held.
+int32_t static_scratch(char** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(SCLBM_EDEVICE, "device %d out of range", dev);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "static scratch address");
+        if (!p) return fail(SCLBM_EDEVICE, "static scratch has no device address");
+        g_scratch_dev[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SCLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t sclbm_batch_step_static(sclbm_inst* const* insts, int32_t n,
+                                           const sclbm_tiling* tiling, const int64_t* steps,
+                                           void* stream)
+{
+    if (!steps) return fail(SCLBM_EINVAL, "steps is NULL");
+    size_t ib, oi, oc, total;
+    int ni;
+    int32_t rc = batch_layout(insts, n, tiling, &ib, &oi, &oc, &total, &ni);
+    if (rc) return rc;
+    const size_t used = oi + sizeof(BatchItem) * (size_t)ni;  // no barrier state here
+    if (used > SCLBM_STATIC_SCRATCH_BYTES)
+        return fail(SCLBM_ESIZE, "batch tables of %zu bytes exceed the static scratch of %u bytes",
+                    used, (unsigned)SCLBM_STATIC_SCRATCH_BYTES);
+    int64_t max_steps = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!insts[k]->inited) return fail(SCLBM_ESTATE, "instance %d not initialised", k);
+        if (steps[k] < 0) return fail(SCLBM_EINVAL, "steps[%d] < 0", k);
+        max_steps = std::max(max_steps, steps[k]);
+    }
+    if (max_steps == 0) return SCLBM_OK;
+    const int storage = insts[0]->d.storage;
+    int nstacked = 0;
+    for (int k = 0; k < n; ++k) nstacked += tiling[k].stacked != 0;
+    const int kind = nstacked == n ? B_STACKED : nstacked == 0 ? B_SWEEP : B_MIXED;
+    hipStream_t st = (hipStream_t)stream;
+
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    char* dev = nullptr;
+    rc = static_scratch(&dev);
+    if (rc) return rc;
+    // tables in the static host stage, laid out as in a plan's workspace
+    const size_t isz = batch_inst_size(storage);
+    for (int k = 0; k < n; ++k) {
+        const sclbm_inst* h = insts[k];
+        void* dst = g_stage + isz * k;
+        if (storage == SCLBM_F64)
+            fill_batch_inst<double, double>(h, h->cd, tiling[k], steps[k], dst);
+        else if (storage == SCLBM_F32)
+            fill_batch_inst<float, float>(h, h->cf, tiling[k], steps[k], dst);
+        else
+            fill_batch_inst<_Float16, float>(h, h->cf, tiling[k], steps[k], dst);
+    }
+    BatchItem* items = reinterpret_cast<BatchItem*>(g_stage + oi);
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        const sclbm_inst* h = insts[k];
+        const int ns = (h->d.nx + tiling[k].tile_x - 1) / tiling[k].tile_x;
+        const int nc = (h->d.ny + tiling[k].tile_y - 1) / tiling[k].tile_y;
+        for (int tt = 0; tt < ns * nc; ++tt) items[m++] = BatchItem{k, tt};
+    }
+    // one upload; the stage may be rewritten by the next call once it is done
+    hipError_t e = hipMemcpyAsync(dev, g_stage, used, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "static batch upload");
+    const BatchItem* ditems = reinterpret_cast<const BatchItem*>(dev + oi);
+    for (int64_t s = 0; s < max_steps && e == hipSuccess; ++s)
+        e = launch_batch_step(storage, kind, dev, ditems, ni, s, st);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    for (int k = 0; k < n; ++k) {
+        sclbm_inst* h = insts[k];
+        h->t += steps[k];
+        h->cur ^= (int)(steps[k] & 1);
+        if (h->d.boundary == SCLBM_WALLS_Y) h->wall_steps += steps[k];
+    }
+    return SCLBM_OK;
+}

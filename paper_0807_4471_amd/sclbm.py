@@ -119,6 +119,8 @@ def _load():
         "sclbm_batch_info": ([vp, ctypes.POINTER(i32)], i32),
         "sclbm_batch_set_mode": ([vp, i32], i32),
         "sclbm_batch_set_barrier_limit": ([vp, ctypes.c_uint32], i32),
+        "sclbm_batch_step_static": ([ctypes.POINTER(vp), i32, ctypes.POINTER(Tiling),
+                                     ctypes.POINTER(i64), vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -412,3 +414,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_step_static(sims, tilings=None, steps=1, stream=None):
+    """Advance Simulations together as one STEPWISE batch without any device
+    workspace: the batch tables go into the library's static device array
+    (sclbm_batch_step_static).  Results equal Batch(..., mode="stepwise")."""
+    sims = list(sims)
+    n = len(sims)
+    if tilings is None:
+        tilings = [default_batch_tiling(s.nx, s.ny) for s in sims]
+    if isinstance(steps, int):
+        steps = [steps] * n
+    arr = (ctypes.c_void_p * n)(*[s.handle.value for s in sims])
+    tl = (Tiling * n)(*[Tiling(*t) for t in tilings])
+    st = (ctypes.c_int64 * n)(*[int(v) for v in steps])
+    check(lib.sclbm_batch_step_static(arr, n, tl, st, _stream(stream)), "batch_step_static")
+

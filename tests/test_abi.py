@@ -175,3 +175,30 @@ def test_batch_rejects_a_repeated_instance(L):
     finally:
         for h in hs:
             L.lib.sclbm_release(h)
+
+
+def test_static_batch_rejects_before_device_work(L):
+    """sclbm_batch_step_static refuses, before any device work: tables larger
+    than its static array (ESIZE), a repeated instance, NULL steps."""
+    d = L.make_desc(8192, 4096, storage="f16dev")
+    need = L.state_bytes(d)
+    hs = [ctypes.c_void_p() for _ in range(3)]
+    for k, h in enumerate(hs):
+        fake = ctypes.c_void_p((1 << 34) * (k + 1))   # never dereferenced
+        assert L.lib.sclbm_bind(ctypes.byref(d), fake, need, ctypes.byref(h)) == L.OK
+    try:
+        # stacked 32 x 4 tiles: 256 x 1024 tiles per instance, 6 MiB of tables
+        tl = (L.Tiling * 3)(*[L.Tiling(32, 4, 4, 1) for _ in range(3)])
+        arr = (ctypes.c_void_p * 3)(*[h.value for h in hs])
+        steps = (ctypes.c_int64 * 3)(1, 1, 1)
+        assert L.lib.sclbm_batch_step_static(arr, 3, tl, steps, None) == L.ESIZE
+        assert "static scratch" in L.last_error()
+        same = (ctypes.c_void_p * 2)(hs[0].value, hs[0].value)
+        assert L.lib.sclbm_batch_step_static(same, 2, tl, steps, None) == L.EINVAL
+        assert L.lib.sclbm_batch_step_static(arr, 3, tl, None, None) == L.EINVAL
+        # fits, but the instances were never initialised: refused as well
+        one = (ctypes.c_void_p * 1)(hs[0].value)
+        assert L.lib.sclbm_batch_step_static(one, 1, tl, steps, None) == L.ESTATE
+    finally:
+        for h in hs:
+            L.lib.sclbm_release(h)

@@ -1,80 +1,160 @@
 """Shear observables of the sheared two-species cell (moving top wall) on the
 GPU, in every storage, against the FP64 oracle: mean shear stress on the
-moving wall over the last steps, and the apparent viscosity from the
-row-mean stress and shear-rate profiles.  The oracle side computes both from
-its own wall-momentum accumulator and row profiles, with the definitions
-written out here."""
+moving wall, and the apparent viscosity from the row-mean stress and
+shear-rate profiles.  The oracle side computes both from its own
+wall-momentum accumulator and row profiles, with the definitions written
+out here.
+
+Three horizons, three kinds of bound:
+  * 100 steps: element by element.  Densities within the accumulated
+    rounding bound (helpers.accumulated_bound: one-step bound summed over
+    the steps, amplified as the oracle measures for a perturbation of the
+    same cell); the wall stress within 6 such population errors per site and
+    step (the exchange sums 3 outgoing and 3 reflected populations).
+  * 2000 steps: the demixing dynamics has amplified rounding into a
+    different trajectory, so the observables are compared with the FP64
+    run-to-run spread, measured in the same test as the standard deviation
+    over four oracle seeds.
+  * the plain fluid (G = 0) started from rest: Stokes' first problem, a
+    stable and deterministic flow where no amplification hides a bias.
+    FP64 must follow the closed form; FP32 and FP16 with stochastic rounding
+    the FP64 result (bounds below); FP16 rounded to nearest is reported.
+FP64 differs from the oracle by rounding order and exp only: 1e-9 relative
+throughout."""
+import math
+
 import numpy as np
 import pytest
 
 import oracle
-from helpers import WORKLOAD, banner
+from helpers import (WORKLOAD, accumulated_bound, banner, max_err, oracle_amplification)
 from paper_0807_4471_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-NX, NY, STEPS, LAST = 128, 64, 2000, 500
-# Relative tolerances (stress, viscosity).  FP64 differs from the oracle by
-# rounding order and exp only (measured <= 2.1e-11).  In FP32 and FP16 the
-# error is rounding amplified by the demixing dynamics (a 1-ulp change of the
-# initial state grows by orders of magnitude within 1000 steps), which the
-# arithmetic alone does not bound: the tolerances are 3x the largest error
-# measured over U in {0.01, 0.05, 0.1} (FP32 5.0e-4 / 4.5e-3, FP16
-# deviations 3.2e-2 / 2.2e-2, FP16 with stochastic rounding of every
-# population 5.5e-2 / -).  The latter's apparent viscosity from one final
-# snapshot is dominated by its rounding noise at the lowest shear (measured
-# relative error 1.1 at U = 0.01): it is reported, not asserted.
-TOL = {"f64": (1e-9, 1e-9), "f32": (1.5e-3, 1.5e-2), "f16dev": (0.1, 0.07),
-       "f16sr": (0.17, None)}
+NX, NY = 128, 64
+SEEDS = (11, 12, 13, 14)
 
 
-def oracle_observables(U, seed):
+def oracle_observables(U, seed, steps, last):
     p = oracle.Params(nx=NX, ny=NY, walls=True, wall_u=(0.0, U), **WORKLOAD)
     f = oracle.init(p, inputs.random_densities(NX, NY, seed))
-    oracle.run(p, f, STEPS - LAST)
+    oracle.run(p, f, steps - last)
     wm = np.zeros((2, 2))
-    oracle.run(p, f, LAST, wm)
-    stress = -wm[1, 0] / (NX * LAST)
+    oracle.run(p, f, last, wm)
+    stress = -wm[1, 0] / (NX * last)
     ux_row, sxy_row = oracle.row_profiles(p, f)
-    rho, _, _ = oracle.moments(p, f)
     g = 0.5 * (ux_row[2:] - ux_row[:-2])
     s = sxy_row[1:-1]
     m = np.abs(g) > 0.01 * np.abs(g).max()
     eta = float(np.sum(s[m] * g[m]) / np.sum(g[m] ** 2))
-    return stress, eta, float(rho.sum(axis=0).mean())
+    return stress, eta, oracle.moments(p, f)
 
 
-def gpu_observables(U, seed, storage):
+def gpu_observables(U, seed, storage, steps, last):
     from paper_0807_4471_amd import sclbm
     from paper_0807_4471_amd.observables import shear_observables
     sim = sclbm.Simulation(NX, NY, storage=storage, boundary="walls", wall_u=(0.0, U),
                            rho_ref=(0.7, 0.7), **WORKLOAD)
     sim.init_random(seed)
-    sim.step(STEPS - LAST)
+    sim.step(steps - last)
     sim.reset_wall_accum()
-    sim.step(LAST)
+    sim.step(last)
     out = shear_observables(sim)
+    out["moments"] = sim.moments()
     sim.close()
     return out
 
 
-_ref_cache = {}
+_short, _long = {}, {}
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f16sr"])
 @pytest.mark.parametrize("U", [0.01, 0.05, 0.1])
-def test_shear_observables_against_oracle(U, storage):
-    banner(f"sheared cell {NX}x{NY} U={U} {storage} {STEPS} steps")
-    if U not in _ref_cache:
-        _ref_cache[U] = oracle_observables(U, seed=11)
-    s_ref, eta_ref, rho_mean = _ref_cache[U]
-    got = gpu_observables(U, 11, storage)
-    e_s = abs(got["wall_stress"] - s_ref) / abs(s_ref)
-    e_eta = abs(got["eta_app"] - eta_ref) / abs(eta_ref)
-    print(f"  stress {got['wall_stress']:.9e} vs {s_ref:.9e} (rel {e_s:.2e}); "
-          f"eta {got['eta_app']:.9e} vs {eta_ref:.9e} (rel {e_eta:.2e})", flush=True)
-    assert got["wall_steps"] == LAST and got["bad_sites"] == 0
-    tol_s, tol_eta = TOL[storage]
+def test_short_horizon_elementwise(U, storage):
+    steps = last = 100
+    banner(f"sheared cell {NX}x{NY} U={U} {storage}: {steps} steps, element by element")
+    if U not in _short:
+        s_ref, _, mom = oracle_observables(U, SEEDS[0], steps, last)
+        amp = oracle_amplification(NX, NY, steps, seed=SEEDS[0], boundary="walls",
+                                   **dict(WORKLOAD, wall_u=(0.0, U)))
+        _short[U] = (s_ref, mom, amp)
+    s_ref, mom, amp = _short[U]
+    got = gpu_observables(U, SEEDS[0], storage, steps, last)
+    e = max_err(got["moments"], mom)
+    e_s = abs(got["wall_stress"] - s_ref)
+    if storage == "f64":
+        tol, tol_s = 1e-12, 1e-9 * abs(s_ref)
+    else:
+        tol = accumulated_bound(storage, amp, steps)
+        tol_s = 6.0 * tol
+    print(f"  err {e} (bound {tol:.3g}); stress {got['wall_stress']:.6e} vs {s_ref:.6e} "
+          f"(|d| {e_s:.3g}, bound {tol_s:.3g})", flush=True)
+    assert e["rho"] <= tol and e["u"] <= tol
     assert e_s <= tol_s
-    if tol_eta is not None:
-        assert e_eta <= tol_eta
+    assert got["wall_steps"] == last and got["bad_sites"] == 0
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f16sr"])
+@pytest.mark.parametrize("U", [0.01, 0.05, 0.1])
+def test_long_horizon_within_seed_spread(U, storage):
+    steps, last = 2000, 500
+    banner(f"sheared cell {NX}x{NY} U={U} {storage}: {steps} steps vs the FP64 seed spread")
+    if U not in _long:
+        r = np.array([oracle_observables(U, s, steps, last)[:2] for s in SEEDS])
+        _long[U] = (r[0], r.std(axis=0, ddof=1))
+    (s_ref, eta_ref), (s_sd, eta_sd) = _long[U]
+    got = gpu_observables(U, SEEDS[0], storage, steps, last)
+    d_s, d_eta = abs(got["wall_stress"] - s_ref), abs(got["eta_app"] - eta_ref)
+    print(f"  stress {got['wall_stress']:.6e} vs {s_ref:.6e} (|d| {d_s:.3g}, seed spread "
+          f"{s_sd:.3g}); eta {got['eta_app']:.6e} vs {eta_ref:.6e} (|d| {d_eta:.3g}, seed "
+          f"spread {eta_sd:.3g})", flush=True)
+    assert got["wall_steps"] == last and got["bad_sites"] == 0
+    if storage == "f64":
+        assert d_s <= 1e-9 * abs(s_ref) and d_eta <= 1e-9 * abs(eta_ref)
+    else:
+        assert d_s <= s_sd and d_eta <= eta_sd
+
+
+def test_plain_fluid_stokes_layer():
+    """G = 0, rest state, top wall at U = 0.1 from t = 0: 64 x 1024 channel,
+    50 000 steps, stress over the last 5000.
+
+    FP64 against sigma_w = rho U sqrt(nu / (pi t)): <= 2% (P7).
+    FP32 against FP64: the flow is stable (perturbations decay), so errors do
+    not grow; FP32 rounding of populations of size <= 0.03 is <= 2^-25 * 0.03
+    ~ 1e-9 per population and step, against a wall exchange of 1.5e-4 per
+    site and step: <= 2e-3 even if every step's rounding added coherently
+    over the ~300 steps a wall disturbance takes to diffuse out of the
+    first rows.
+    FP16 with stochastic rounding: unbiased noise of at most one ulp of
+    2^-16 (1.5e-5) per population; the stress averages 64 x 5000 site-steps,
+    so its noise is ~1.5e-5 * sqrt(6 / 3.2e5) ~ 1e-7 against 1.5e-4, plus the
+    flow's linear response to that noise: <= 1e-2 relative.
+    FP16 rounded to nearest: the layer is steady and uniform along x, so
+    every site of a row rounds the same way every step, a coherent bias of
+    up to half an ulp per population and step that no averaging removes; it
+    is printed, not bounded (use stochastic rounding for steady flows)."""
+    from paper_0807_4471_amd import sclbm
+    from paper_0807_4471_amd.observables import mean_wall_stress
+    nx, ny, U, T, last = 64, 1024, 0.1, 50000, 5000
+    banner("Stokes layer, G = 0, 64x1024, 50k steps, every storage")
+    nu = (1.0 - 0.5) / 3.0
+    t = np.arange(T - last, T) + 0.5
+    stokes = 1.4 * U * math.sqrt(nu / math.pi) * float(np.mean(1.0 / np.sqrt(t)))
+    got = {}
+    for storage in ("f64", "f32", "f16sr", "f16dev"):
+        sim = sclbm.Simulation(nx, ny, storage=storage, boundary="walls", wall_u=(0.0, U),
+                               Ga=(0.0, 0.0), Gr=(0.0, 0.0), Gx=0.0, rho0=0.7,
+                               rho_ref=(0.7, 0.7))
+        sim.init_fields(np.full((2, ny, nx), 0.7))
+        sim.step(T - last)
+        sim.reset_wall_accum()
+        sim.step(last)
+        got[storage] = mean_wall_stress(sim.diagnostics(), nx)
+        sim.close()
+    rel = {k: abs(v / got["f64"] - 1.0) for k, v in got.items()}
+    print(f"  Stokes {stokes:.6e}; GPU {got}; relative to FP64 {rel}", flush=True)
+    assert abs(got["f64"] / stokes - 1.0) <= 0.02
+    assert rel["f32"] <= 2e-3
+    assert rel["f16sr"] <= 1e-2

@@ -316,3 +316,70 @@ def test_shift_demixing_needs_small_tau(oracle_lib):
     assert spread(1.5, "shift") > 5.0
     assert spread(2.0, "shift") < 0.1
     assert spread(0.8, "guo") < 0.1
+
+
+def _rot90(a):
+    """Field a[..., y, x] on an L x L periodic lattice rotated by +90 degrees
+    about the origin: b(x', y') = a(x, y) with (x', y') = (-y mod L, x)."""
+    L = a.shape[-1]
+    y, x = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    b = np.empty_like(a)
+    b[..., x, (-y) % L] = a[..., y, x]
+    return b
+
+
+def test_rot90_helper_is_a_rotation():
+    a = np.arange(25.0).reshape(5, 5)
+    # the site (x=1, y=0) goes to (x'=0, y'=1); (x=0, y=1) goes to (x'=4, y'=0)
+    b = _rot90(a)
+    assert b[1, 0] == a[0, 1] and b[0, 4] == a[1, 0]
+    assert np.array_equal(_rot90(_rot90(_rot90(_rot90(a)))), a)
+
+
+def test_rotation_by_90_degrees(oracle_lib):
+    """P12: the force stencil and D2Q9 are invariant under a 90-degree
+    rotation, so a rotated initial field gives the rotated result (densities
+    rotate, velocities rotate as vectors).  The rotated run adds its terms in
+    another order, hence a rounding-level tolerance over few steps."""
+    L, steps = 24, 20
+    p = oracle_lib.Params(nx=L, ny=L, tau=(0.9, 1.15), **BJ)
+    rho = inputs.random_densities(L, L, seed=8)
+    f1 = oracle_lib.init(p, rho)
+    f2 = oracle_lib.init(p, _rot90(rho))
+    oracle_lib.run(p, f1, steps)
+    oracle_lib.run(p, f2, steps)
+    r1, ux1, uy1 = oracle_lib.moments(p, f1)
+    r2, ux2, uy2 = oracle_lib.moments(p, f2)
+    assert np.abs(_rot90(r1) - r2).max() <= 1e-14
+    # u' = R u with R (ux, uy) = (-uy, ux)
+    assert np.abs(_rot90(-uy1) - ux2).max() <= 1e-14
+    assert np.abs(_rot90(ux1) - uy2).max() <= 1e-14
+    assert np.abs(ux1).max() > 1e-4   # forces did drive a flow
+
+
+def test_stokes_first_problem_transient(oracle_lib):
+    """P7, transient: G = 0 fluid at rest between walls, the top wall set
+    moving at U at t = 0.  While the shear layer is thin compared with the
+    channel (4 sqrt(nu t) = 365 << 1024 at t = 5e4), the stress on the moving
+    wall follows Stokes' first problem, sigma_w = rho U sqrt(nu / (pi t)).
+    The flow does not depend on x, so a 4-column channel of 1024 rows stands
+    for the 1024 x 1024 cell.  Averaged over the last 5000 steps; <= 2%."""
+    nx, ny, U, T, last = 4, 1024, 0.1, 50000, 5000
+    p = oracle_lib.Params(nx=nx, ny=ny, walls=True, Ga=(0, 0), Gr=(0, 0), Gx=0.0,
+                          wall_u=(0.0, U))
+    f = oracle_lib.init(p, np.full((2, ny, nx), 0.7))
+    oracle_lib.run(p, f, T - last)
+    wall = np.zeros((2, 2))
+    oracle_lib.run(p, f, last, wall)
+    sigma = -wall[1, 0] / (nx * last)
+    nu = CS2 * (1.0 - 0.5)
+    t = np.arange(T - last, T) + 0.5
+    stokes = 1.4 * U * np.sqrt(nu / np.pi) * np.mean(1.0 / np.sqrt(t))
+    assert abs(sigma / stokes - 1.0) <= 0.02, (sigma, stokes)
+    # the velocity profile is Stokes' erfc layer below the moving wall plane
+    # y = ny - 1/2 (and the bottom wall, 1024 rows away, is not yet reached)
+    from math import erfc
+    ux, _ = oracle_lib.row_profiles(p, f)
+    d = (ny - 0.5) - np.arange(ny)
+    want = np.array([U * erfc(v / (2.0 * np.sqrt(nu * T))) for v in d])
+    assert np.abs(ux - want).max() <= 2e-3 * U

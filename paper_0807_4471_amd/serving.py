@@ -38,7 +38,8 @@ class Request:
     nx: int
     ny: int
     steps: int
-    storage: str = "f32"      # "f32" or "f16dev" (or "f64")
+    storage: str = "f32"      # "f32", "f16sr" (FP16 deviations rounded
+                              # stochastically), "f16dev" or "f64"
     boundary: str = "periodic"
     wall_u: float = 0.0       # top-wall speed for boundary == "walls"
     seed: int = 0
@@ -70,11 +71,13 @@ class Result:
 
 
 def make_trace(n: int, rate: float, seed: int = 4242, side=(64, 1024), steps=(1000, 100000),
-               storages=("f32", "f16dev"), walls_fraction=0.5,
+               storages=("f32", "f16sr"), walls_fraction=0.5,
                wall_speeds=(0.01, 0.05, 0.1)) -> list[Request]:
     """Poisson arrivals at `rate` per second; sizes and step counts
     log-uniform; storage and boundary drawn uniformly; per-request seeds
-    10000 + id."""
+    10000 + id.  FP16 requests store deviations rounded stochastically:
+    round-to-nearest is biased in steady wall-driven flow, which half of the
+    requests are."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []

@@ -14,7 +14,7 @@ def test_trace_is_seeded_and_in_range():
            [(r.arrival, r.nx, r.steps, r.storage, r.boundary, r.seed) for r in b]
     assert all(64 <= r.nx <= 1024 and r.nx == r.ny for r in a)
     assert all(1000 <= r.steps <= 100000 for r in a)
-    assert {r.storage for r in a} == {"f32", "f16dev"}
+    assert {r.storage for r in a} == {"f32", "f16sr"}
     assert {r.boundary for r in a} == {"periodic", "walls"}
     assert all((r.wall_u in (0.01, 0.05, 0.1)) == (r.boundary == "walls") for r in a)
     arr = np.array([r.arrival for r in a])

@@ -97,3 +97,18 @@ def batch_mix(seed: int = 2026, n: int = 64) -> list[dict]:
     tau = rng.uniform(0.8, 1.2, (n, 2))
     return [dict(nx=int(sides[i]), ny=int(sides[i]), rho0=float(rho0[i]), Gx=float(gx[i]),
                  tau=(float(tau[i, 0]), float(tau[i, 1])), seed=1000 + i) for i in range(n)]
+
+
+def ripple_slab_densities(nx: int, ny: int, rho_in: float, rho_out: float, amp: float = 2.0,
+                          width: float = 1.5, mode: int = 1) -> np.ndarray:
+    """Slab of species A (density rho_in; B has rho_out there, and the reverse
+    outside) between y = ny/4 and 3 ny/4, both interfaces displaced outward
+    by amp * sin(2 pi mode x / nx) (a varicose ripple), tanh profiles."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    d = amp * np.sin(2.0 * np.pi * mode * x / nx)
+    y1, y2 = ny / 4.0 - d, 3.0 * ny / 4.0 + d
+    s = 0.5 * (np.tanh((y - y1) / width) - np.tanh((y - y2) / width))
+    rho = np.empty((2, ny, nx))
+    rho[0] = rho_out + (rho_in - rho_out) * s
+    rho[1] = rho_in + (rho_out - rho_in) * s
+    return rho

@@ -101,3 +101,24 @@ def laplace_fit(radii, jumps):
     ss = np.sum((dP - dP.mean()) ** 2)
     r2 = 1.0 - np.sum((dP - M @ [sigma, c0]) ** 2) / ss if ss > 0 else 1.0
     return float(sigma), float(c0), float(r2)
+
+
+# --------------------------------------------------- sign of the surface tension
+
+def interface_crossings(rhoA, rhoB) -> tuple:
+    """(crossings along y, crossings along x) of the order parameter
+    phi = rho_A - rho_B: the number of neighbouring site pairs (periodic)
+    whose phi differ in sign.  A flat slab has exactly 2 per column along y
+    and none along x; a positive surface tension relaxes a rippled slab to
+    that state, a negative one breaks it into ever more interface."""
+    s = np.sign(np.asarray(rhoA, dtype=np.float64) - np.asarray(rhoB, dtype=np.float64))
+    return int((s != np.roll(s, 1, axis=0)).sum()), int((s != np.roll(s, 1, axis=1)).sum())
+
+
+def ripple_amplitude(rhoA, mode: int = 1) -> float:
+    """Fourier coefficient on sin(2 pi mode x / nx) of the A mass per column
+    (the varicose ripple of inputs.ripple_slab_densities)."""
+    rA = np.asarray(rhoA, dtype=np.float64)
+    nx = rA.shape[1]
+    M = rA.sum(axis=0)
+    return float(np.sum(M * np.sin(2.0 * np.pi * mode * np.arange(nx) / nx)) * 2.0 / nx)

@@ -153,6 +153,10 @@ def oracle_amplification(nx, ny, steps, seed=1, rho=None, boundary="periodic", e
         oracle.run(p, f1, 1)
         d = np.abs(oracle.moments(p, f1)[0] - oracle.moments(p, f0)[0]).max()
         amp[m] = max(amp[m - 1], d / d0)
+    # the envelope is a linear-response bound: valid only while the grown
+    # perturbation is still small against the fields themselves
+    if d > 1e-3:
+        raise ValueError(f"perturbation grew to {d:.3g}: nonlinear, no rounding bound from it")
     if with_moments:
         return amp, oracle.moments(p, f0)
     return amp

@@ -76,3 +76,36 @@ def test_surface_tension_decreases_with_rho0(oracle_lib):
     fits = _laplace_fit(jobs)
     sig = [fits[tuple(sorted(dict(PAPER, rho0=r0).items()))][0] for r0 in (0.6, 0.7, 0.75)]
     assert sig[0] > sig[1] > sig[2] > 0.0, sig
+
+
+@pytest.mark.parametrize("amp_name", ["rho0", "sqrt_rho0"])
+def test_flat_interface_stability_gives_the_sign_of_sigma(amp_name):
+    """The sign of the surface tension without any pressure formula: a slab
+    of A in B with a varicose ripple (64 x 64, caption couplings, rho0 = 0.7).
+    With sigma > 0 the ripple decays and the slab relaxes to two flat
+    interfaces (2 sign changes of phi per column along y, none along x);
+    with sigma < 0 interfaces multiply.  Psi amplitude rho0 (the workloads'):
+    flat and stable.  Amplitude sqrt(rho0) (the paper's text): the slab
+    breaks into a micro-structure whose interface keeps growing, so no
+    Laplace state exists there, and sigma(rho0) under that amplitude cannot
+    come from droplets."""
+    import oracle
+    from paper_0807_4471_amd import inputs
+    from paper_0807_4471_amd.observables import interface_crossings, ripple_amplitude
+    L, r0 = 64, 0.7
+    p = oracle.Params(nx=L, ny=L, rho0=r0, psi_amp=r0 if amp_name == "rho0" else r0 ** 0.5,
+                      **PAPER)
+    f = oracle.init(p, inputs.ripple_slab_densities(L, L, 1.2, 0.2))
+    a0 = ripple_amplitude(oracle.moments(p, f)[0][0])
+    hist = []
+    for _ in range(4):
+        oracle.run(p, f, 2000)
+        r = oracle.moments(p, f)[0]
+        hist.append((interface_crossings(r[0], r[1]), ripple_amplitude(r[0])))
+    (cy, cx), a = hist[-1]
+    if amp_name == "rho0":
+        assert (cy, cx) == (2 * L, 0)
+        assert abs(a) <= 1e-3 * abs(a0)
+    else:
+        assert cy > 4 * 2 * L and cx > 4 * 2 * L
+        assert hist[-1][0][0] > hist[0][0][0]      # and still growing

@@ -56,16 +56,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def build(verbose: bool = False) -> str:
+# Debug variant: the kernels fill their Psi/rho ring with NaN before staging,
+# so a ring cell read without having been staged poisons the result.
+POISON_LIB = os.path.join(HERE, "libsclbm_lds_poison.so")
+
+
+def build(verbose: bool = False, lib: str = LIB, defines=(), subdir: str = "") -> str:
+    """Compile the units (in parallel) and link `lib`; `defines` are extra
+    preprocessor flags for every unit, `subdir` keeps their objects apart."""
     from concurrent.futures import ThreadPoolExecutor
     t0 = time.time()
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build", subdir)
     os.makedirs(bdir, exist_ok=True)
     cmds, objs = [], []
     for src, extra, oname in UNITS:
         obj = os.path.join(bdir, oname)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmds.append([HIPCC, *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC, *FLAGS, *defines, *extra, *lang, "-c", os.path.join(CSRC, src),
+                     "-o", obj])
         objs.append(obj)
     if verbose:
         for c in cmds:
@@ -82,13 +90,20 @@ def build(verbose: bool = False) -> str:
             lines = [ln for ln in p.stderr.splitlines() if "packed-fp32-ops" not in ln]
             if lines:
                 print("\n".join(lines), flush=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
-    return LIB
+        print(f"built {lib} in {time.time() - t0:.1f}s", flush=True)
+    return lib
+
+
+def build_poison(verbose: bool = False) -> str:
+    """The NaN-poisoned-LDS debug library (tests only)."""
+    return build(verbose, POISON_LIB, ["-DSCLBM_POISON_LDS=1"], "poison")
 
 
 if __name__ == "__main__":
     build(verbose="-q" not in sys.argv)
+    if "--poison" in sys.argv:
+        build_poison(verbose="-q" not in sys.argv)

@@ -649,6 +649,27 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
 }
 
+// Debug builds (-DSCLBM_POISON_LDS=1) fill the Psi/rho ring with NaN before
+// a tile stages anything, so a force that reads a ring cell its own pass
+// never staged (a missed halo row or column) poisons that site and fails
+// the parity tests.  Regular builds compile this away.
+#ifndef SCLBM_POISON_LDS
+#define SCLBM_POISON_LDS 0
+#endif
+template <class A2>
+__device__ __forceinline__ void poison_ring(A2* psi, A2* rho, int cells)
+{
+    if constexpr (SCLBM_POISON_LDS) {
+        using A = decltype(A2{}.x);
+        const A nan = (A)__builtin_nan("");
+        for (int k = threadIdx.x; k < cells; k += blockDim.x) {
+            psi[k] = A2{nan, nan};
+            rho[k] = A2{nan, nan};
+        }
+        __syncthreads();
+    }
+}
+
 template <int CW>
 __device__ __forceinline__ void block_reduce(double* acc, double (*red)[NDIAG], double* out)
 {
@@ -678,6 +699,7 @@ __global__ __launch_bounds__(64 * CW) void sweep_kernel(Inst<typename T::S, type
     __shared__ typename T::A2 lpsi[6][64 * CW];
     __shared__ typename T::A2 lrho[6][64 * CW];
     __shared__ double red[CW][NDIAG];
+    poison_ring(&lpsi[0][0], &lrho[0][0], 6 * 64 * CW);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int chunk = b / I.nstrips, strip = b - chunk * I.nstrips;
     double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -724,6 +746,7 @@ __global__ __launch_bounds__(64 * RW) void tile_kernel(Inst<typename T::S, typen
     __shared__ typename T::A2 lpsi[RW + 4][64];
     __shared__ typename T::A2 lrho[RW + 4][64];
     __shared__ double red[RW][NDIAG];
+    poison_ring(&lpsi[0][0], &lrho[0][0], (RW + 4) * 64);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int chunk = b / I.nstrips, strip = b - chunk * I.nstrips;
     double acc[NDIAG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -897,6 +920,7 @@ __device__ __forceinline__ void batch_item(const BatchInst<typename T::S, typena
         I.fout = const_cast<S*>(a);
     }
     I.t += s;
+    poison_ring(&lpsi[0][0], &lrho[0][0], (KIND == B_STACKED ? 2 : 6) * 256);
     int strip, chunk;
     if (ROW) {
         chunk = tile / I.nstrips;

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsclbm.so")
+# SCLBM_LIBRARY selects another build of the same library (the tests use it
+# for the NaN-poisoned-LDS debug build); default: the in-tree libsclbm.so.
+LIB_PATH = os.environ.get("SCLBM_LIBRARY") or os.path.join(_HERE, "libsclbm.so")
 
 OK, EINVAL, ESIZE, EDEVICE, ENONFINITE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PERIODIC, WALLS_Y = 0, 1

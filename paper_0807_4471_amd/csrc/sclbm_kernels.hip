@@ -36,6 +36,7 @@
 // barrier per step, or one ordinary launch per step); read-out passes of
 // the sweep (moments, FP64 diagnostics, the order parameter); the fixed-order
 // reduction of per-block FP64 partials; the initialiser.
+#include <algorithm>
 #include <type_traits>
 
 #include "sclbm_internal.h"
@@ -120,32 +121,37 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t species_rsrc(const char* base,
 // write through it with system coherence (CPOL_WT).
 constexpr int CPOL_WT = 16;
 
+// voff: the per-lane part of the byte offset (a column); soff: the part
+// that is uniform across the wave (row and plane), passed in a scalar
+// register so that no per-load vector add is needed.  A lane whose voff is
+// DROP is out of range whatever soff is (both are < 2^31).
 template <class S>
-__device__ __forceinline__ S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff)
+__device__ __forceinline__ S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
     if constexpr (sizeof(S) == 8)
         return __builtin_bit_cast(
-            S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+            S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
     else if constexpr (sizeof(S) == 4)
         return __builtin_bit_cast(
-            S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+            S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
     else
         return __builtin_bit_cast(
-            S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0));
+            S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
 }
 
 template <class S, int CP = 0>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, S v)
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                       S v)
 {
     if constexpr (sizeof(S) == 8) {
         typedef unsigned u2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0,
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff,
                                               CP);
     } else if constexpr (sizeof(S) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, 0,
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff,
                                               CP);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, 0,
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff,
                                               CP);
     }
 }
@@ -159,13 +165,17 @@ __device__ __forceinline__ typename T::A rcp(typename T::A v)
         return __builtin_amdgcn_rcpf(v);
 }
 
+// exp of the pseudo-potential: ocml exp in FP64; in FP32 the hardware
+// base-2 exponential (v_exp_f32) of v log2(e), whose error (about one ulp
+// for the arguments here, -rho/rho0 in [-10, 0]) is far below the FP32
+// storage rounding of a step.
 template <class T>
 __device__ __forceinline__ typename T::A expo(typename T::A v)
 {
     if constexpr (std::is_same<typename T::A, double>::value)
         return exp(v);
     else
-        return expf(v);
+        return __builtin_amdgcn_exp2f(v * 1.4426950408889634f);
 }
 
 // Register representation of the populations.  FP64 / FP32 storage: v_i =
@@ -184,6 +194,11 @@ struct Sweep {
     // previous row is finished) except in FP64, where three resident rows of
     // doubles leave no registers for a fourth.
     static constexpr bool PF = !std::is_same<A, double>::value;
+    // The uniform (row and plane) part of population offsets goes in the
+    // buffer instructions' scalar offset for FP64 and FP32 storage, which
+    // saves a vector add per access; FP16 keeps the whole offset per lane,
+    // which measured faster for its 2-byte accesses.
+    static constexpr bool SOFF = !DEV;
     static constexpr int NC = 64 * CW;
 
     const Inst<S, A>& I;
@@ -260,7 +275,10 @@ struct Sweep {
             for (int i = 0; i < 9; ++i) {
                 const uint32_t ro = CY_[i] > 0 ? om : CY_[i] < 0 ? op : o0;
                 const uint32_t co = CX_[i] > 0 ? cm : CX_[i] < 0 ? cp : cw;
-                R[s * 9 + i] = bload<S>(rin[s], co + (ro + (uint32_t)(i * plane_b)));
+                if constexpr (SOFF)
+                    R[s * 9 + i] = bload<S>(rin[s], co, ro + (uint32_t)(i * plane_b));
+                else
+                    R[s * 9 + i] = bload<S>(rin[s], co + (ro + (uint32_t)(i * plane_b)), 0u);
             }
     }
 
@@ -527,7 +545,7 @@ struct Sweep {
                             myw += (double)CY_[i] * 2.0 * (double)c.rho_base[s] *
                                    (CX_[i] == 0 ? W1 : W2);
                     }
-                    const uint32_t dst = col + (ro_off + (uint32_t)((k - 9 * s) * plane_b));
+                    const uint32_t dsoff = ro_off + (uint32_t)((k - 9 * s) * plane_b);
                     if constexpr (DEV) {
                         _Float16 h;
                         if constexpr (T::SR) {
@@ -539,10 +557,10 @@ struct Sweep {
                         } else {
                             h = (_Float16)val;
                         }
-                        bstore<_Float16, SCP>(rout[s], dst, h);
+                        bstore<_Float16, SCP>(rout[s], col + dsoff, 0u, h);
                         qsum += (float)h;  // exact: sum of binary16 values
                     } else {
-                        bstore<S, SCP>(rout[s], dst, (S)val);
+                        bstore<S, SCP>(rout[s], col, dsoff, (S)val);
                     }
                 }
                 if constexpr (DEV) {
@@ -556,9 +574,9 @@ struct Sweep {
                     typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
                     h2_t hv = {(_Float16)0, (_Float16)0};
                     hv = __builtin_amdgcn_cvt_sr_f16_f32(hv, h0, r, false);
-                    bstore<_Float16, SCP>(rout[s], sw_ + soff, hv[0]);
+                    bstore<_Float16, SCP>(rout[s], sw_ + soff, 0u, hv[0]);
                 } else {
-                    bstore<S, SCP>(rout[s], sw_ + soff, (S)f[0]);
+                    bstore<S, SCP>(rout[s], sw_, soff, (S)f[0]);
                 }
             }
             if constexpr (WALLS) {
@@ -722,7 +740,7 @@ __device__ __forceinline__ void tile_body(const Inst<typename T::S, typename T::
     static_assert(RW >= 4, "four waves stage the halo rows");
     using A = typename T::A;
     Sweep<T, 1, WALLS, MODE, RW + 4, SCP> sw(I, strip, lpsi, lrho, acc);
-    const int w = threadIdx.x >> 6;  // uniform per wave
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     const int y0 = chunk * RW;
     A P[18];
     sw.load(y0 + w);
@@ -999,7 +1017,10 @@ static int batch_grid_t()
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<T, KIND>, 256, 0) !=
         hipSuccess)
         return 0;
-    return per_cu * cus;
+    // Every co-resident workgroup meets at each grid barrier, whose cost
+    // grows with their number: at most 2 per CU (3 per CU measured 15%
+    // slower per step on the uneven batch mix).
+    return std::min(per_cu, 2) * cus;
 }
 
 template <class T>

@@ -148,6 +148,7 @@ def oracle_amplification(nx, ny, steps, seed=1, rho=None, boundary="periodic", e
     f1 = oracle.init(p, rho + pert)
     d0 = np.abs(oracle.moments(p, f1)[0] - oracle.moments(p, f0)[0]).max()
     amp = np.ones(steps + 1)
+    d = d0
     for m in range(1, steps + 1):
         oracle.run(p, f0, 1)
         oracle.run(p, f1, 1)

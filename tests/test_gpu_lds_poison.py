@@ -2,7 +2,7 @@
 its kernels fill the Psi/rho ring with NaN before staging, so a missed halo
 row or column turns the result non-finite.  The parity cases of
 lds_poison_cases.py (every sweep width, stacked tiles, walls, ragged
-lattices, fused and read-out passes, both batch modes) must match the
+lattices, fused and read-out passes, step-wise batches) must match the
 oracle with it.  Run in a child process, which loads that library instead
 of the regular one."""
 import os

@@ -322,6 +322,28 @@ def tune_batch(mixes, steps: int | None = None, table: dict | None = None,
     return rec
 
 
+def policy_mixes(storage: str) -> list:
+    """The three mixes a batch policy is scored on: the 64-instance uneven
+    batch workload, a serving-like group of 8 lattices (64^2..1024^2, half
+    of them between walls) and one 1024^2 lattice; every instance
+    initialised from its seed."""
+    from . import sclbm
+    from .inputs import batch_mix
+    W = dict(Ga=(-12.55, -11.80), Gr=(11.70, 10.95), Gx=0.58, rho0=0.70)
+
+    def sim(nx, ny, seed, boundary="periodic", **kw):
+        s = sclbm.Simulation(nx, ny, storage=storage, boundary=boundary,
+                             wall_u=(0.0, 0.05) if boundary == "walls" else (0.0, 0.0),
+                             **{**W, **kw})
+        return s.init_random(seed)
+
+    mix64 = [sim(m["nx"], m["ny"], m["seed"], rho0=m["rho0"], Gx=m["Gx"], tau=m["tau"])
+             for m in batch_mix()]
+    serving_like = [sim(n, n, 10 + k, "walls" if k % 2 else "periodic")
+                    for k, n in enumerate((64, 96, 150, 230, 350, 520, 700, 1024))]
+    return [mix64, serving_like, [sim(1024, 1024, 7)]]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 256, 512, 1024, 2048, 4096])
@@ -331,9 +353,22 @@ def main():
     ap.add_argument("--storage", nargs="+", default=["f32", "f16dev", "f64"])
     ap.add_argument("--boundary", nargs="+", default=["periodic"])
     ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--policy", action="store_true",
+                    help="tune the batch policy (tile policy x execution mode) of each storage "
+                         "on the three mixes of policy_mixes, instead of single lattices")
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args()
     table = load_table()
+    if a.policy:
+        for st in a.storage:
+            mixes = policy_mixes(st)
+            rec = tune_batch(mixes, table=table, verbose=a.verbose)
+            print(f"{policy_key(st)}: {rec}", flush=True)
+            save_table(table)
+            for m in mixes:
+                for s in m:
+                    s.close()
+        return
     if a.shapes:
         shapes = [tuple(int(v) for v in sh.lower().split("x")) for sh in a.shapes]
     else:

@@ -96,6 +96,10 @@ def parse():
                     help="force coupling of the droplets of the sigma(rho0) sweep")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=20000)
+    ap.add_argument("--batch-modes", default="stepwise,persistent",
+                    help="batch execution modes to time (a profiler run leaves out "
+                         "'persistent', whose cooperative launch rocprofv3 does not survive "
+                         "at exit)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-load", type=float, default=0.8)
@@ -105,6 +109,9 @@ def parse():
     ap.add_argument("--serve-capacity-glups", type=float, default=None,
                     help="batch capacity that sets the arrival rate (default: the "
                          "measured batch rate, else 20)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further 20k-step timed regions of the headline lattice, for the "
+                         "run-to-run spread (0: none, e.g. under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=250)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -525,16 +532,23 @@ def run_batch(a, torch, sclbm):
     info = b.info()
     ms_b, _ = timed(torch, lambda: b.step(a.batch_steps))
     b.status()
-    b.close()
     # the same instances, continued for the same number of steps in one
-    # persistent cooperative launch (its own best tuned policy)
-    from paper_0807_4471_amd import autotune
-    tl_p, _ = autotune.batch_plan(sims, mode="persistent")
-    bp = sclbm.Batch(sims, tl_p, mode="persistent")
-    info_p = bp.info()
-    ms_p, _ = timed(torch, lambda: bp.step(a.batch_steps))
-    bp.status()
-    bp.close()
+    # persistent cooperative launch (its own best tuned policy), or again
+    # step-wise (untimed) when that mode is left out, so that they end where
+    # the instances run one at a time below end
+    info_p, ms_p = None, None
+    if "persistent" not in a.batch_modes.split(","):
+        b.step(a.batch_steps)
+        b.status()
+    b.close()
+    if "persistent" in a.batch_modes.split(","):
+        from paper_0807_4471_amd import autotune
+        tl_p, _ = autotune.batch_plan(sims, mode="persistent")
+        bp = sclbm.Batch(sims, tl_p, mode="persistent")
+        info_p = bp.info()
+        ms_p, _ = timed(torch, lambda: bp.step(a.batch_steps))
+        bp.status()
+        bp.close()
     seq = make(tiling="auto")
     ms_s, _ = timed(torch, lambda: [s.step(a.batch_steps) for s in seq])
     ms_s2, _ = timed(torch, lambda: [s.step(a.batch_steps) for s in seq])
@@ -566,7 +580,7 @@ def run_batch(a, torch, sclbm):
                        "batch policy; each instance also run alone for comparison",
            "instances": len(mix), "sites": sites, "steps": a.batch_steps,
            "batched_mlups": round(lups / (ms_b * 1e-3) / 1e6, 1),
-           "persistent_launch_mlups": round(lups / (ms_p * 1e-3) / 1e6, 1),
+           "persistent_launch_mlups": round(lups / (ms_p * 1e-3) / 1e6, 1) if ms_p else None,
            "sequential_mlups": round(2 * lups / ((ms_s + ms_s2) * 1e-3) / 1e6, 1),
            "speedup": round((ms_s + ms_s2) / 2 / ms_b, 3),
            "bitwise_equal_to_sequential": bool(same),
@@ -723,12 +737,13 @@ def main():
         out["rho0_sweep"] = rho0_sweep(a, torch, sclbm, (sim, ms_total, d))
     # run-to-run spread: five more timed regions of 20k steps on the same
     # lattice (after the sweep has read its state)
-    reps = sorted(timed(torch, lambda: sim.step(20000))[0] / 20000 for _ in range(5))
-    out["repeats"] = {"runs": 5, "steps_each": 20000,
-                      "median_us_per_step": round(reps[2] * 1e3, 3),
-                      "min_us_per_step": round(reps[0] * 1e3, 3),
-                      "max_us_per_step": round(reps[-1] * 1e3, 3)}
-    log(f"headline repeats: {out['repeats']}")
+    if a.repeats > 0:
+        reps = sorted(timed(torch, lambda: sim.step(20000))[0] / 20000 for _ in range(a.repeats))
+        out["repeats"] = {"runs": a.repeats, "steps_each": 20000,
+                          "median_us_per_step": round(reps[len(reps) // 2] * 1e3, 3),
+                          "min_us_per_step": round(reps[0] * 1e3, 3),
+                          "max_us_per_step": round(reps[-1] * 1e3, 3)}
+        log(f"headline repeats: {out['repeats']}")
     sim.close()
     del sim
     torch.cuda.empty_cache()

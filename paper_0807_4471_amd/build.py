@@ -98,6 +98,26 @@ def build(verbose: bool = False, lib: str = LIB, defines=(), subdir: str = "") -
     return lib
 
 
+CEILING = os.path.join(HERE, "hbm_ceiling")
+
+
+def build_ceiling(verbose: bool = False) -> str:
+    """The bandwidth-ceiling probe (csrc/hbm_ceiling.hip), a stand-alone
+    program: plain copy and the step's 18-plane pull with no arithmetic."""
+    tmp = CEILING + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           os.path.join(CSRC, "hbm_ceiling.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        sys.stderr.write(p.stdout + p.stderr)
+        raise subprocess.CalledProcessError(p.returncode, cmd)
+    os.replace(tmp, CEILING)
+    return CEILING
+
+
 def build_poison(verbose: bool = False) -> str:
     """The NaN-poisoned-LDS debug library (tests only)."""
     return build(verbose, POISON_LIB, ["-DSCLBM_POISON_LDS=1"], "poison")

@@ -2,6 +2,7 @@
 
     python -m paper_0807_4471_amd.profsummary db <run_results.db> [name-substring]
     python -m paper_0807_4471_amd.profsummary stats <kernel_stats.csv> [name-substring]
+    python -m paper_0807_4471_amd.profsummary trace <kernel_trace.csv> [name-substring]
     python -m paper_0807_4471_amd.profsummary traffic \\
         --fetch <FETCH_SIZE counter_collection.csv> --write <WRITE_SIZE ...csv> \\
         --copy-fetch <csv> --copy-write <csv> --copy-bytes 1073741824 \\
@@ -9,7 +10,8 @@
 
 `db` groups the dispatches of a rocpd database by (kernel name, grid size,
 workgroup size), so launches of one kernel template on different lattices
-are not averaged together.  `stats` prints a kernel_stats.csv in microseconds.
+are not averaged together; `trace` does the same for a kernel_trace.csv.
+`stats` prints a kernel_stats.csv in microseconds.
 
 `traffic` turns two counter runs (FETCH_SIZE, then WRITE_SIZE: KiB moved
 between L2 and the memory fabric per dispatch) into bytes per launch of the
@@ -54,6 +56,24 @@ def cmd_stats(path, sub=""):
         print(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
               f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
               f"{float(r['Percentage']):.2f} |")
+
+
+def cmd_trace(path, sub=""):
+    groups = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if sub and sub not in r["Kernel_Name"]:
+            continue
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        g = int(r.get("Grid_Size_X") or r["Grid_Size"])
+        w = int(r.get("Workgroup_Size_X") or r["Workgroup_Size"])
+        groups[(r["Kernel_Name"], g, w)].append(dur)
+    print("| kernel | grid | workgroup | calls | avg us | median us | min us | max us |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|")
+    for (name, g, w), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        d = sorted(d)
+        short = name.replace("sclbm::", "").split("(")[0]
+        print(f"| `{short}` | {g} | {w} | {len(d)} | {sum(d) / len(d):.3f} | "
+              f"{d[len(d) // 2]:.3f} | {d[0]:.3f} | {d[-1]:.3f} |")
 
 
 def _per_dispatch(path):
@@ -120,6 +140,8 @@ def main(argv):
         cmd_db(*rest)
     elif cmd == "stats":
         cmd_stats(*rest)
+    elif cmd == "trace":
+        cmd_trace(*rest)
     elif cmd == "traffic":
         cmd_traffic(rest)
     else:

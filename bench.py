@@ -113,7 +113,8 @@ def parse():
                     help="further 20k-step timed regions of the headline lattice, for the "
                          "run-to-run spread (0: none, e.g. under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=250)
+    ap.add_argument("--cpu-scale", type=float, default=1.0,
+                    help="scale of the oracle timing sample's step counts")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     return ap.parse_args()
@@ -641,21 +642,46 @@ def run_serving(a, torch, sclbm, rate_lups):
     return out
 
 
-def cpu_baseline(nx, steps, rho0):
+def cpu_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the share of a shared host)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(env))) if env.isdigit() and int(env) > 0 else max(1, n)
+
+
+def cpu_baseline(rho0, scale: float = 1.0):
+    """The FP64 oracle on the host (the same seeded 5% random start, caption
+    couplings) at 64^2, 512^2 and 1024^2, single-threaded and on all the
+    process's cores (OpenMP over rows; the arithmetic is the same).  Step
+    counts are bounded so the whole sample is ~25 s of host time; `value` is
+    the all-core rate on the headline's 512^2 lattice."""
     import numpy as np
     import oracle
     from paper_0807_4471_amd import inputs
     oracle.build(force=False)
-    p = oracle.Params(nx=nx, ny=nx, **dict(WORKLOAD, rho0=rho0))
-    f = oracle.init(p, inputs.random_densities(nx, nx, 1))
-    t0 = time.perf_counter()
-    oracle.run(p, f, steps)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(f).all()
-    return {"value": round(nx * nx * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, {nx}x{nx} periodic, same couplings and seeded init, "
-                      f"{steps} steps ({dt:.1f} s, single thread on {host_cpu()})"}
+    nthr = cpu_threads()
+    runs = []
+    for nx, s1, sn in ((64, 1000, 1000), (512, 150, 600), (1024, 40, 200)):
+        p = oracle.Params(nx=nx, ny=nx, **dict(WORKLOAD, rho0=rho0))
+        for threads, steps in ((1, s1), (nthr, sn)):
+            steps = max(1, int(steps * scale))
+            used = oracle.set_threads(threads)
+            f = oracle.init(p, inputs.random_densities(nx, nx, 1))
+            t0 = time.perf_counter()
+            oracle.run(p, f, steps)
+            dt = time.perf_counter() - t0
+            assert np.isfinite(f).all()
+            runs.append({"nx": nx, "threads": used, "steps": steps, "seconds": round(dt, 3),
+                         "mlups": round(nx * nx * steps / dt / 1e6, 4)})
+    oracle.set_threads(0)
+    head = [r for r in runs if r["nx"] == 512][-1]
+    return {"value": head["mlups"], "unit": "MLUPS", "cores": head["threads"], "kind": "oracle",
+            "sample": f"FP64 oracle, {head['nx']}x{head['nx']} periodic, same couplings and "
+                      f"seeded init, {head['steps']} steps on {head['threads']} threads "
+                      f"({head['seconds']} s); also 1 thread and 64^2, 1024^2 in runs "
+                      f"(host: {host_cpu()})",
+            "runs": runs}
 
 
 def host_cpu() -> str:
@@ -795,7 +821,7 @@ def main():
     if not a.no_serve:
         out["serving"] = run_serving(a, torch, sclbm, rate_lups)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nx, a.cpu_steps, a.rho0)
+        out["cpu_baseline"] = cpu_baseline(a.rho0, a.cpu_scale)
     print(json.dumps(out), flush=True)
 
 

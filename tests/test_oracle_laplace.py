@@ -25,6 +25,7 @@ def _droplet(args):
     import oracle
     from paper_0807_4471_amd import inputs
     R, kw, steps, L, rin, rout = args
+    oracle.set_threads(1)       # one per worker process: the pool runs the droplets side by side
     p = oracle.Params(nx=L, ny=L, **kw)
     f = oracle.init(p, inputs.droplet_densities(L, L, R, rin, rout))
     oracle.run(p, f, steps)
@@ -41,7 +42,10 @@ def _droplet(args):
 
 
 def _laplace_fit(jobs):
-    with get_context("fork").Pool(min(6, len(jobs))) as pool:
+    # fresh worker processes: a forked copy of a process whose OpenMP runtime
+    # has started threads would wait for them forever at its first parallel
+    # region
+    with get_context("spawn").Pool(min(6, len(jobs))) as pool:
         res = pool.map(_droplet, jobs)
     out = {}
     for job, (R, dP) in zip(jobs, res):

@@ -30,27 +30,31 @@ template <> struct Vec<4> { typedef unsigned T; };
 template <> struct Vec<8> { typedef unsigned T __attribute__((ext_vector_type(2))); };
 template <> struct Vec<16> { typedef unsigned T __attribute__((ext_vector_type(4))); };
 
-template <int B>
+// Cache-policy bits of the buffer instructions (gfx950): 1 sc0, 2 nt, 16 sc1.
+template <int B, int CP = 0>
 __device__ __forceinline__ typename Vec<B>::T load(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
-    if constexpr (B == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
-    else if constexpr (B == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-    else if constexpr (B == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-    else return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    if constexpr (B == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, CP);
+    else if constexpr (B == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, CP);
+    else if constexpr (B == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP);
+    else return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP);
 }
-template <int B>
+template <int B, int CP = 0>
 __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, typename Vec<B>::T v)
 {
-    if constexpr (B == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
-    else if constexpr (B == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
-    else if constexpr (B == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
-    else __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+    if constexpr (B == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, CP);
+    else if constexpr (B == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, CP);
+    else if constexpr (B == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, CP);
+    else __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, CP);
 }
 
 // ES-byte elements, V per lane; rows 0..ny+1 (ghost rows 0 and ny+1),
 // columns at element offset 32 + x; a workgroup of 256 lanes sweeps H rows
 // of a strip of 256 V columns, loading the next row before storing this one.
-template <int ES, int V>
+// SX: planes read with their column shift (the step's pattern) or without
+// (every load aligned like the stores); LP / SP: cache policy of the loads /
+// stores.
+template <int ES, int V, bool SX = true, int LP = 0, int SP = 0>
 __global__ __launch_bounds__(256) void pull18(const char* fin, char* fout, int nx, int ny, int pitch,
                                               int plane, int H, int nstrips)
 {
@@ -69,15 +73,15 @@ __global__ __launch_bounds__(256) void pull18(const char* fin, char* fout, int n
         for (int k = 0; k < 18; ++k) {
             const int i = k % 9;
             const uint32_t off =
-                (uint32_t)(((y + 1 - CYv[i]) * pitch + 32 + x0 - CXv[i] + k * plane) * ES);
-            dst[k] = load<B>(rin, act ? off : 0x80000000u);
+                (uint32_t)(((y + 1 - CYv[i]) * pitch + 32 + x0 - (SX ? CXv[i] : 0) + k * plane) * ES);
+            dst[k] = load<B, LP>(rin, act ? off : 0x80000000u);
         }
     };
     auto st = [&](int y, const T* src) {
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
             const uint32_t off = (uint32_t)(((y + 1) * pitch + 32 + x0 + k * plane) * ES);
-            store<B>(rout, act ? off : 0x80000000u, src[k]);
+            store<B, SP>(rout, act ? off : 0x80000000u, src[k]);
         }
     };
     if (y0 < y1) ld(y0, R);
@@ -97,13 +101,64 @@ __global__ __launch_bounds__(256) void copy16(const uint4* __restrict__ a, uint4
         b[i] = a[i];
 }
 
+// Copy with U 16-byte loads in flight per lane before their stores, through
+// buffer instructions with cache policies LP / SP; n16 16-byte words, the
+// whole buffer < 2^31 bytes.
+template <int U, int LP, int SP>
+__global__ __launch_bounds__(256) void copy16u(const char* a, char* b, uint32_t n16)
+{
+    const auto ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(a), (short)0, (int)(n16 * 16u), 0x00020000);
+    const auto rb = __builtin_amdgcn_make_buffer_rsrc(b, (short)0, (int)(n16 * 16u), 0x00020000);
+    const uint32_t stride = gridDim.x * 256u;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n16; i += U * stride) {
+        Vec<16>::T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = i + u * stride;
+            v[u] = load<16, LP>(ra, j < n16 ? j * 16u : 0x80000000u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = i + u * stride;
+            store<16, SP>(rb, j < n16 ? j * 16u : 0x80000000u, v[u]);
+        }
+    }
+}
+
+template <int U, int LP, int SP>
+double time_copyu(char* a, char* b, uint32_t n16, int grid, int reps, const char* tag)
+{
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    for (int k = 0; k < 3; ++k)
+        hipLaunchKernelGGL((copy16u<U, LP, SP>), dim3(grid), dim3(256), 0, 0, a, b, n16);
+    CK(hipDeviceSynchronize());
+    CK(hipEventRecord(e0, 0));
+    for (int k = 0; k < reps; ++k)
+        hipLaunchKernelGGL((copy16u<U, LP, SP>), dim3(grid), dim3(256), 0, 0, a, b, n16);
+    CK(hipEventRecord(e1, 0));
+    CK(hipEventSynchronize(e1));
+    float ms;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    CK(hipGetLastError());
+    const double us = ms / reps * 1e3;
+    const double tbs = 2.0 * n16 * 16.0 / (us * 1e-6) / 1e12;
+    printf("copy%s, %5d workgroups: %8.2f us  %.3f TB/s\n", tag, grid, us, tbs);
+    fflush(stdout);
+    CK(hipEventDestroy(e0));
+    CK(hipEventDestroy(e1));
+    return tbs;
+}
+
 struct Best {
     double tbs = 0;
     int v = 0, h = 0;
 };
 
-template <int ES, int V>
-double time_pull(char* a, char* b, int nx, int ny, int pitch, int plane, int H)
+template <int ES, int V, bool SX = true, int LP = 0, int SP = 0>
+double time_pull(char* a, char* b, int nx, int ny, int pitch, int plane, int H,
+                 const char* tag = "")
 {
     const int nstrips = (nx + 256 * V - 1) / (256 * V);
     const int nb = nstrips * ((ny + H - 1) / H);
@@ -112,11 +167,11 @@ double time_pull(char* a, char* b, int nx, int ny, int pitch, int plane, int H)
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
     for (int k = 0; k < 3; ++k)
-        hipLaunchKernelGGL((pull18<ES, V>), dim3(nb), dim3(256), 0, 0, a, b, nx, ny, pitch, plane, H, nstrips);
+        hipLaunchKernelGGL((pull18<ES, V, SX, LP, SP>), dim3(nb), dim3(256), 0, 0, a, b, nx, ny, pitch, plane, H, nstrips);
     CK(hipDeviceSynchronize());
     CK(hipEventRecord(e0, 0));
     for (int k = 0; k < reps; ++k)
-        hipLaunchKernelGGL((pull18<ES, V>), dim3(nb), dim3(256), 0, 0, (k & 1) ? b : a, (k & 1) ? a : b,
+        hipLaunchKernelGGL((pull18<ES, V, SX, LP, SP>), dim3(nb), dim3(256), 0, 0, (k & 1) ? b : a, (k & 1) ? a : b,
                            nx, ny, pitch, plane, H, nstrips);
     CK(hipEventRecord(e1, 0));
     CK(hipEventSynchronize(e1));
@@ -125,8 +180,8 @@ double time_pull(char* a, char* b, int nx, int ny, int pitch, int plane, int H)
     CK(hipGetLastError());
     const double us = ms / reps * 1e3;
     const double tbs = 2.0 * 18 * nx * (double)ny * ES / (us * 1e-6) / 1e12;
-    printf("pull18 %d-byte elements, %d per lane, H=%3d, %6d workgroups: %8.2f us  %.3f TB/s\n", ES,
-           V, H, nb, us, tbs);
+    printf("pull18%s %d-byte elements, %d per lane, H=%3d, %6d workgroups: %8.2f us  %.3f TB/s\n", tag,
+           ES, V, H, nb, us, tbs);
     fflush(stdout);
     CK(hipEventDestroy(e0));
     CK(hipEventDestroy(e1));
@@ -198,9 +253,40 @@ int main(int argc, char** argv)
     sweep<2, 2>(f16, a, b, nx, ny, pitch, plane);
     sweep<2, 4>(f16, a, b, nx, ny, pitch, plane);
     sweep<2, 8>(f16, a, b, nx, ny, pitch, plane);
+    // variants: copies with several loads in flight and cache policies; the
+    // pull without column shifts (aligned loads) and with cache policies
+    const int reps = nx <= 1024 ? 1000 : 20;
+    const uint32_t n16 = (uint32_t)((size_t)18 * plane * 4 / 16);
+    double vc[6] = {0, 0, 0, 0, 0, 0};
+    for (int g : {1024, 2048, 4096}) {
+        vc[0] = fmax(vc[0], time_copyu<1, 0, 0>(a, b, n16, g, reps, " buffer 1 in flight"));
+        vc[1] = fmax(vc[1], time_copyu<4, 0, 0>(a, b, n16, g, reps, " buffer 4 in flight"));
+        vc[2] = fmax(vc[2], time_copyu<4, 2, 2>(a, b, n16, g, reps, " buffer 4 in flight, nt loads+stores"));
+        vc[3] = fmax(vc[3], time_copyu<4, 0, 2>(a, b, n16, g, reps, " buffer 4 in flight, nt stores"));
+        vc[4] = fmax(vc[4], time_copyu<4, 0, 16>(a, b, n16, g, reps, " buffer 4 in flight, sc1 stores"));
+        vc[5] = fmax(vc[5], time_copyu<8, 0, 0>(a, b, n16, g, reps, " buffer 8 in flight"));
+    }
+    double vp[10];
+    vp[0] = time_pull<4, 1, false>(a, b, nx, ny, pitch, plane, 4, " aligned");
+    vp[1] = time_pull<4, 1, true, 0, 2>(a, b, nx, ny, pitch, plane, 4, " nt stores");
+    vp[2] = time_pull<4, 1, true, 0, 16>(a, b, nx, ny, pitch, plane, 4, " sc1 stores");
+    vp[3] = time_pull<4, 1, true, 2, 2>(a, b, nx, ny, pitch, plane, 4, " nt loads+stores");
+    vp[4] = time_pull<4, 1, false, 0, 2>(a, b, nx, ny, pitch, plane, 4, " aligned, nt stores");
+    vp[5] = time_pull<2, 1, false>(a, b, nx, ny, pitch, plane, 4, " aligned");
+    vp[6] = time_pull<2, 1, true, 0, 2>(a, b, nx, ny, pitch, plane, 4, " nt stores");
+    vp[7] = time_pull<2, 1, true, 0, 16>(a, b, nx, ny, pitch, plane, 4, " sc1 stores");
+    vp[8] = time_pull<2, 8, true, 0, 2>(a, b, nx, ny, pitch, plane, 4, " nt stores");
+    vp[9] = time_pull<4, 1, true, 0, 0>(a, b, nx, ny, pitch, plane, 4, " (again)");
     printf("{\"side\": %d, \"copy_TBps\": %.3f, \"pull_f32_TBps\": %.3f, \"pull_f32_best\": [%d, %d], "
-           "\"pull_f16_TBps\": %.3f, \"pull_f16_best\": [%d, %d]}\n",
-           nx, copy_best, f32.tbs, f32.v, f32.h, f16.tbs, f16.v, f16.h);
+           "\"pull_f16_TBps\": %.3f, \"pull_f16_best\": [%d, %d], "
+           "\"copy_buffer\": {\"u1\": %.3f, \"u4\": %.3f, \"u4_nt\": %.3f, \"u4_nt_store\": %.3f, "
+           "\"u4_sc1_store\": %.3f, \"u8\": %.3f}, "
+           "\"pull_h4\": {\"f32_aligned\": %.3f, \"f32_nt_store\": %.3f, \"f32_sc1_store\": %.3f, "
+           "\"f32_nt\": %.3f, \"f32_aligned_nt_store\": %.3f, \"f16_aligned\": %.3f, "
+           "\"f16_nt_store\": %.3f, \"f16_sc1_store\": %.3f, \"f16x8_nt_store\": %.3f, "
+           "\"f32_again\": %.3f}}\n",
+           nx, copy_best, f32.tbs, f32.v, f32.h, f16.tbs, f16.v, f16.h, vc[0], vc[1], vc[2], vc[3],
+           vc[4], vc[5], vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6], vp[7], vp[8], vp[9]);
     CK(hipFree(a));
     CK(hipFree(b));
     return 0;

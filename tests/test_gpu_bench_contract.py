@@ -20,7 +20,7 @@ def test_bench_line_contract():
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "300", "--warmup", "20",
            "--no-sweep", "--no-dram", "--no-shear", "--no-rheology", "--no-ageing",
            "--no-laplace", "--no-batch", "--no-serve", "--no-guo", "--no-small",
-           "--cpu-steps", "3"]
+           "--cpu-scale", "0.01", "--repeats", "2"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
@@ -42,8 +42,17 @@ def test_bench_line_contract():
         <= 0.01 * rf["achieved"]
     assert rf["traffic"] is None or rf["traffic"] > 0
     rp = d["repeats"]
-    assert rp["runs"] == 5
+    assert rp["runs"] == 2
     assert rp["min_us_per_step"] <= rp["median_us_per_step"] <= rp["max_us_per_step"]
     cb = d["cpu_baseline"]
-    assert cb["kind"] == "oracle" and cb["unit"] == "MLUPS" and cb["cores"] == 1
-    assert cb["value"] > 0 and "3 steps" in cb["sample"]
+    assert cb["kind"] == "oracle" and cb["unit"] == "MLUPS" and cb["cores"] >= 1
+    assert cb["value"] > 0 and f"on {cb['cores']} threads" in cb["sample"]
+    # the oracle at three sizes, single-threaded and on all the process's threads
+    runs = cb["runs"]
+    assert sorted({r["nx"] for r in runs}) == [64, 512, 1024]
+    for nx in (64, 512, 1024):
+        th = sorted(r["threads"] for r in runs if r["nx"] == nx)
+        assert th[0] == 1 and th[-1] == cb["cores"]
+    assert all(r["steps"] >= 1 and r["mlups"] > 0 for r in runs)
+    head = [r for r in runs if r["nx"] == 512 and r["threads"] == cb["cores"]]
+    assert head and head[-1]["mlups"] == cb["value"]

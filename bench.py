@@ -742,6 +742,10 @@ def main():
     with_traffic(roof, traffic_for(f"{storage}_{nx}" + ("_guo" if a.forcing == "guo" else "")))
     # ping-pong footprint (2 copies x 18 populations) vs the 256 MiB Infinity Cache
     roof["cache_resident"] = BYTES_PER_LUP[storage] * nx * nx < 256 * 2 ** 20
+    if roof["cache_resident"]:
+        roof["note"] = ("the ping-pong state fits the 256 MB Infinity Cache, so this fraction "
+                        "is against the HBM peak but not bound by HBM; the HBM-roofline claims "
+                        "are the DRAM-resident lattices of dram_resident")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),

@@ -319,8 +319,8 @@ int32_t sclbm_batch_release(sclbm_batch* batch);
 /* Bytes of the static device array behind sclbm_batch_step_static. */
 #define SCLBM_STATIC_SCRATCH_BYTES (4u << 20)
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, hosts that forbid hipMalloc): plan and run
+/* For callers that cannot allocate device memory (tight serving loops,
+ * hosts that forbid hipMalloc): plan and run
  * a batch in one call, as sclbm_batch_plan + sclbm_batch_step in STEPWISE
  * mode would, with the batch tables (per-instance parameters and tile
  * table) in a static device array of SCLBM_STATIC_SCRATCH_BYTES instead of
@@ -334,7 +334,8 @@ int32_t sclbm_batch_release(sclbm_batch* batch);
  * Calls no allocation routine: the tables are built in a static host array,
  * copied by one upload, and hip_stream (which must belong to the current
  * device) is synced once after that upload; the step launches are then
- * enqueued asynchronously.  Every call on a GPU shares that GPU's array and
+ * enqueued asynchronously.  Because of that one sync the call cannot itself
+ * be recorded into a HIP graph.  Every call on a GPU shares that GPU's array and
  * overwrites it, so calls whose work overlaps on one GPU (other streams,
  * other host threads) race; host calls are serialised by a lock.  Results
  * are bitwise those of sclbm_batch_step. */

@@ -10,7 +10,8 @@ shorter than the stencil.
 import numpy as np
 import pytest
 
-from helpers import WORKLOAD, banner, gpu_run, max_err, oracle_run
+from helpers import (WORKLOAD, accumulated_bound, banner, gpu_run, max_err, oracle_amplification,
+                     oracle_run)
 
 pytestmark = pytest.mark.gpu
 
@@ -215,8 +216,11 @@ def test_walls_short_lattices_all_tilings(storage, ny, tiling):
     _, m = gpu_run(nx, ny, 12, storage=storage, tiling=tiling, **kw)
     _, _, ref = oracle_run(nx, ny, 12, **kw)
     e = max_err(m, ref)
-    tol = {"f64": 1e-12, "f32": 1e-4, "f16dev": 1e-2, "f16sr": 1e-2}[storage]
-    assert e["rho"] <= tol, e
+    if storage == "f64":
+        tol = 1e-12
+    else:   # one-step bound summed over the steps, amplified as the oracle measures
+        tol = accumulated_bound(storage, oracle_amplification(nx, ny, 12, **kw), 12)
+    assert e["rho"] <= tol, (e, tol)
 
 
 @pytest.mark.parametrize("case", ["workload", "unequal_tau", "body_force", "walls"])

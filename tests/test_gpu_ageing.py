@@ -5,14 +5,18 @@ batch equal to the same instances advanced alone."""
 import numpy as np
 import pytest
 
-from helpers import WORKLOAD, banner, oracle_run
+from helpers import WORKLOAD, accumulated_bound, banner, oracle_amplification, oracle_run
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("boundary", ["periodic", "walls"])
-def test_order_parameter_against_oracle(storage, tol, boundary):
+def test_order_parameter_against_oracle(storage, boundary):
+    """phi after 40 steps against the oracle's rho_A - rho_B: FP64 to
+    2e-12; FP32 within twice the derived density bound (phi differences two
+    densities).  The overlap with the oracle's phi, normalised, differs from
+    one by at most max|dphi| sum|phi| / sum(phi^2)."""
     import torch
     from paper_0807_4471_amd import inputs, sclbm
     banner(f"{storage} {boundary} order parameter")
@@ -30,10 +34,20 @@ def test_order_parameter_against_oracle(storage, tol, boundary):
     ref = torch.from_numpy(np.ascontiguousarray(phi_ref_host)).cuda()
     s_ref, s_sq = sim.order_parameter(phi_ref=ref, phi_out=phi)
     got = phi.cpu().numpy()
-    assert np.abs(got - phi_ref_host).max() <= tol * 10, np.abs(got - phi_ref_host).max()
+    if storage == "f64":
+        tol_phi = 2e-12
+    else:
+        amp = oracle_amplification(nx, ny, steps, rho=rho, boundary=boundary, **kw)
+        tol_phi = 2.0 * accumulated_bound(storage, amp, steps)
+    e_phi = float(np.abs(got - phi_ref_host).max())
+    tol_ratio = tol_phi * float(np.sum(np.abs(phi_ref_host)) / np.sum(phi_ref_host ** 2))
+    ratio = s_ref / float(np.sum(phi_ref_host ** 2))
+    print(f"  max|dphi| {e_phi:.3g} (bound {tol_phi:.3g}); overlap - 1 = {ratio - 1.0:.3g} "
+          f"(bound {tol_ratio:.3g})", flush=True)
+    assert e_phi <= tol_phi
     assert abs(s_sq - float(np.sum(got * got))) <= 1e-12 * s_sq
     assert abs(s_ref - float(np.sum(got * phi_ref_host))) <= 1e-12 * abs(s_ref)
-    assert abs(s_ref / float(np.sum(phi_ref_host ** 2)) - 1.0) <= tol * 100
+    assert abs(ratio - 1.0) <= tol_ratio
     sim.close()
 
 

@@ -603,7 +603,14 @@ def run_batch(a, torch, sclbm):
            "healthy": {"instances": len(healthy), "sites": h_sites,
                        "batched_mlups": round(h_sites * a.batch_steps / (ms_h * 1e-3) / 1e6, 1)},
            "plan": info, "persistent_plan": info_p}
-    log(f"batch: {out}")
+    # rooflines of the batch kernels: every site of every instance reads and
+    # writes its 18 populations once per step; the counter traffic was taken
+    # on the step-wise kernel over this mix
+    out["roofline"] = roofline(sites, "f32", ms_b / a.batch_steps, ny=1)
+    if info.get("mode") == "stepwise":
+        with_traffic(out["roofline"], traffic_for("batch_f32_64"))
+    if ms_p:
+        out["persistent_roofline"] = roofline(sites, "f32", ms_p / a.batch_steps, ny=1)
     return out
 
 

@@ -95,6 +95,53 @@ __global__ __launch_bounds__(256) void pull18(const char* fin, char* fout, int n
     if (y < y1) st(y, R);
 }
 
+// The same pull with the loads of the next TWO rows in flight while a row
+// is stored (prefetch depth 2; pull18 keeps one row ahead).
+template <int ES, int V>
+__global__ __launch_bounds__(256) void pull18d2(const char* fin, char* fout, int nx, int ny, int pitch,
+                                                int plane, int H, int nstrips)
+{
+    constexpr int B = ES * V;
+    using T = typename Vec<B>::T;
+    const int strip = blockIdx.x % nstrips, chunk = blockIdx.x / nstrips;
+    const int x0 = (strip * 256 + (int)threadIdx.x) * V;
+    const int nrec = 18 * plane * ES;
+    const auto rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(fin), (short)0, nrec, 0x00020000);
+    const auto rout = __builtin_amdgcn_make_buffer_rsrc(fout, (short)0, nrec, 0x00020000);
+    const bool act = x0 < nx;
+    const int y0 = chunk * H, y1 = min(y0 + H, ny);
+    T A[18], Bq[18], C[18];
+    auto ld = [&](int y, T* dst) {
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            const int i = k % 9;
+            const uint32_t off =
+                (uint32_t)(((y + 1 - CYv[i]) * pitch + 32 + x0 - CXv[i] + k * plane) * ES);
+            dst[k] = load<B>(rin, act ? off : 0x80000000u);
+        }
+    };
+    auto st = [&](int y, const T* src) {
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+            const uint32_t off = (uint32_t)(((y + 1) * pitch + 32 + x0 + k * plane) * ES);
+            store<B>(rout, act ? off : 0x80000000u, src[k]);
+        }
+    };
+    if (y0 < y1) ld(y0, A);
+    if (y0 + 1 < y1) ld(y0 + 1, Bq);
+    int y = y0;
+    for (; y + 3 <= y1; y += 3) {
+        if (y + 2 < y1) ld(y + 2, C);
+        st(y, A);
+        if (y + 3 < y1) ld(y + 3, A);
+        st(y + 1, Bq);
+        if (y + 4 < y1) ld(y + 4, Bq);
+        st(y + 2, C);
+    }
+    if (y < y1) st(y, A);
+    if (y + 1 < y1) st(y + 1, Bq);
+}
+
 __global__ __launch_bounds__(256) void copy16(const uint4* __restrict__ a, uint4* __restrict__ b, size_t n)
 {
     for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
@@ -123,6 +170,37 @@ __global__ __launch_bounds__(256) void copy16u(const char* a, char* b, uint32_t 
             store<16, SP>(rb, j < n16 ? j * 16u : 0x80000000u, v[u]);
         }
     }
+}
+
+template <int ES, int V>
+double time_pull_d2(char* a, char* b, int nx, int ny, int pitch, int plane, int H)
+{
+    const int nstrips = (nx + 256 * V - 1) / (256 * V);
+    const int nb = nstrips * ((ny + H - 1) / H);
+    const int reps = nx <= 1024 ? 1000 : 20;
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    for (int k = 0; k < 3; ++k)
+        hipLaunchKernelGGL((pull18d2<ES, V>), dim3(nb), dim3(256), 0, 0, a, b, nx, ny, pitch, plane, H, nstrips);
+    CK(hipDeviceSynchronize());
+    CK(hipEventRecord(e0, 0));
+    for (int k = 0; k < reps; ++k)
+        hipLaunchKernelGGL((pull18d2<ES, V>), dim3(nb), dim3(256), 0, 0, (k & 1) ? b : a, (k & 1) ? a : b,
+                           nx, ny, pitch, plane, H, nstrips);
+    CK(hipEventRecord(e1, 0));
+    CK(hipEventSynchronize(e1));
+    float ms;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    CK(hipGetLastError());
+    const double us = ms / reps * 1e3;
+    const double tbs = 2.0 * 18 * nx * (double)ny * ES / (us * 1e-6) / 1e12;
+    printf("pull18 prefetch depth 2, %d-byte elements, %d per lane, H=%3d, %6d workgroups: %8.2f us  %.3f TB/s\n",
+           ES, V, H, nb, us, tbs);
+    fflush(stdout);
+    CK(hipEventDestroy(e0));
+    CK(hipEventDestroy(e1));
+    return tbs;
 }
 
 template <int U, int LP, int SP>
@@ -277,6 +355,15 @@ int main(int argc, char** argv)
     vp[7] = time_pull<2, 1, true, 0, 16>(a, b, nx, ny, pitch, plane, 4, " sc1 stores");
     vp[8] = time_pull<2, 8, true, 0, 2>(a, b, nx, ny, pitch, plane, 4, " nt stores");
     vp[9] = time_pull<4, 1, true, 0, 0>(a, b, nx, ny, pitch, plane, 4, " (again)");
+    // prefetch depth 2 at the long chunks a sweep uses (one row ahead: the
+    // pull18 lines of the sweep above at the same H)
+    double d2[6];
+    d2[0] = time_pull_d2<4, 1>(a, b, nx, ny, pitch, plane, 64);
+    d2[1] = time_pull_d2<4, 1>(a, b, nx, ny, pitch, plane, 128);
+    d2[2] = time_pull_d2<4, 1>(a, b, nx, ny, pitch, plane, 256);
+    d2[3] = time_pull_d2<2, 1>(a, b, nx, ny, pitch, plane, 64);
+    d2[4] = time_pull_d2<2, 1>(a, b, nx, ny, pitch, plane, 128);
+    d2[5] = time_pull_d2<2, 1>(a, b, nx, ny, pitch, plane, 256);
     printf("{\"side\": %d, \"copy_TBps\": %.3f, \"pull_f32_TBps\": %.3f, \"pull_f32_best\": [%d, %d], "
            "\"pull_f16_TBps\": %.3f, \"pull_f16_best\": [%d, %d], "
            "\"copy_buffer\": {\"u1\": %.3f, \"u4\": %.3f, \"u4_nt\": %.3f, \"u4_nt_store\": %.3f, "
@@ -284,9 +371,11 @@ int main(int argc, char** argv)
            "\"pull_h4\": {\"f32_aligned\": %.3f, \"f32_nt_store\": %.3f, \"f32_sc1_store\": %.3f, "
            "\"f32_nt\": %.3f, \"f32_aligned_nt_store\": %.3f, \"f16_aligned\": %.3f, "
            "\"f16_nt_store\": %.3f, \"f16_sc1_store\": %.3f, \"f16x8_nt_store\": %.3f, "
-           "\"f32_again\": %.3f}}\n",
+           "\"f32_again\": %.3f}, \"depth2_f32_h64_128_256\": [%.3f, %.3f, %.3f], "
+           "\"depth2_f16_h64_128_256\": [%.3f, %.3f, %.3f]}\n",
            nx, copy_best, f32.tbs, f32.v, f32.h, f16.tbs, f16.v, f16.h, vc[0], vc[1], vc[2], vc[3],
-           vc[4], vc[5], vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6], vp[7], vp[8], vp[9]);
+           vc[4], vc[5], vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6], vp[7], vp[8], vp[9],
+           d2[0], d2[1], d2[2], d2[3], d2[4], d2[5]);
     CK(hipFree(a));
     CK(hipFree(b));
     return 0;

@@ -134,7 +134,8 @@ def timed(torch, fn):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    torch.cuda._sleep(200_000)
+    if hasattr(torch.cuda, "_sleep"):
+        torch.cuda._sleep(200_000)
     e0.record(st)
     fn()
     e1.record(st)

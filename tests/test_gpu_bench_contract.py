@@ -41,6 +41,8 @@ def test_bench_line_contract():
     assert abs(rf["achieved"] - 144 * 512 * 512 / (d["ms_per_step"] * 1e-3) / 1e9) \
         <= 0.01 * rf["achieved"]
     assert rf["traffic"] is None or rf["traffic"] > 0
+    dw = d["device_warmup"]
+    assert dw["ms"] >= 0 and "exactly" in dw["what"]
     rp = d["repeats"]
     assert rp["runs"] == 2
     assert rp["min_us_per_step"] <= rp["median_us_per_step"] <= rp["max_us_per_step"]

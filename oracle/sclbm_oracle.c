@@ -37,7 +37,13 @@
  * 8th-order isotropy of the repulsion stencil; zero net force; mass and
  * momentum conservation; uniform state; shear-wave viscosity
  * c_s^2 (tau - 1/2); exact Couette profile between walls; Galilean advection;
- * Laplace law dP ~ 1/R.  The read-outs (physical velocity with the half
+ * Stokes' first problem (wall stress rho U sqrt(nu / (pi t)) and the erfc
+ * layer); a 90-degree rotation of the lattice rotating the result; Laplace
+ * law dP ~ 1/R; the sign of the surface tension from whether a rippled flat
+ * interface relaxes; 1 and N OpenMP threads bitwise equal.  Every function
+ * below is pinned by at least one of these; the long-run physics built on
+ * them (arrest, ageing curves, the sigma(rho0) curve) has no pin in the
+ * paper beyond figures: parity unpinned there.  The read-outs (physical velocity with the half
  * force, sigma_xy, totals, row profiles, u_bar, I_AB) are checked with forces
  * and a body force on against a whole-array brute-force evaluation of their
  * definitions on tiny lattices, periodic and with walls.  Those definitions

@@ -17,7 +17,8 @@
  * The state is the post-streaming, pre-collision population set f_is(r,t)
  * of Eq. (1): time t is the number of completed steps.
  *
- * Parity status per function is stated in sclbm_oracle.c.
+ * The pins of each function, and what is parity unpinned, are listed at the
+ * top of sclbm_oracle.c.
  */
 #ifndef SCLBM_ORACLE_H
 #define SCLBM_ORACLE_H

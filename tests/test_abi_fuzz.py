@@ -67,3 +67,47 @@ def test_random_descriptors(L, nx, ny, boundary, storage, tau, Ga, Gr, Gx, rho0,
     assert not h.value
     assert L.lib.sclbm_bind(ctypes.byref(d), fake, need, ctypes.byref(h)) == L.OK and h.value
     assert L.lib.sclbm_release(h) == L.OK
+
+
+def expected_tiling_ok(nx, ny, W, H, waves, stacked, throttle, wt):
+    if stacked not in (0, 1) or throttle not in (0, 1) or wt not in (0, 1):
+        return False
+    if wt and not stacked:
+        return False
+    if stacked:
+        if waves not in (4, 8) or H != waves or W > 60:
+            return False
+    else:
+        if waves not in (1, 2, 4) or W > 64 * waves - 4 or H < min(4, ny):
+            return False
+    return W >= min(32, nx)
+
+
+@settings(max_examples=400, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(nx=st.integers(1, 600), ny=st.integers(2, 600), W=st.integers(-5, 300),
+       H=st.integers(-5, 300), waves=st.integers(-1, 9), stacked=st.integers(-1, 2),
+       throttle=st.integers(-1, 2), wt=st.integers(-1, 2))
+def test_random_tilings(L, nx, ny, W, H, waves, stacked, throttle, wt):
+    """sclbm_set_tiling accepts exactly the tilings the header's rules allow,
+    and a refused one leaves the current tiling in place."""
+    d = L.make_desc(nx, ny, storage="f32")
+    need = L.state_bytes(d)
+    h = ctypes.c_void_p()
+    assert L.lib.sclbm_bind(ctypes.byref(d), ctypes.c_void_p(1 << 20), need,
+                            ctypes.byref(h)) == L.OK
+    try:
+        before = L.Tiling()
+        assert L.lib.sclbm_get_tiling(h, ctypes.byref(before)) == L.OK
+        rc = L.lib.sclbm_set_tiling(h, ctypes.byref(L.Tiling(W, H, waves, stacked, throttle, wt)))
+        after = L.Tiling()
+        assert L.lib.sclbm_get_tiling(h, ctypes.byref(after)) == L.OK
+        got = (after.tile_x, after.tile_y, after.waves, after.stacked, after.throttle,
+               after.write_through)
+        if expected_tiling_ok(nx, ny, W, H, waves, stacked, throttle, wt):
+            assert rc == L.OK and got == (W, H, waves, stacked, throttle, wt)
+        else:
+            assert rc == L.EINVAL
+            assert got == (before.tile_x, before.tile_y, before.waves, before.stacked,
+                           before.throttle, before.write_through)
+    finally:
+        L.lib.sclbm_release(h)

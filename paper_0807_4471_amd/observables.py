@@ -35,13 +35,18 @@ def apparent_viscosity(ux_row: np.ndarray, sxy_row: np.ndarray, rho_mean: float)
     return eta, eta / float(rho_mean)
 
 
+def shear_profiles(sim):
+    """(row means of u_x, row means of sigma_xy, mean total density) of a
+    walls Simulation's current state (syncs)."""
+    m = sim.moments()
+    return (m["ux"].mean(axis=1), m["sxy"].mean(axis=1),
+            float((m["rhoA"] + m["rhoB"]).mean()))
+
+
 def shear_observables(sim) -> dict:
     """Wall stress and apparent viscosity of a walls Simulation (syncs)."""
     d = sim.diagnostics()
-    m = sim.moments()
-    ux_row = m["ux"].mean(axis=1)
-    sxy_row = m["sxy"].mean(axis=1)
-    rho_mean = float((m["rhoA"] + m["rhoB"]).mean())
+    ux_row, sxy_row, rho_mean = shear_profiles(sim)
     eta, nu = apparent_viscosity(ux_row, sxy_row, rho_mean)
     return {"wall_stress": mean_wall_stress(d, sim.nx), "eta_app": eta, "nu_app": nu,
             "wall_steps": int(d["wall_steps"]), "bad_sites": int(d["bad_sites"])}
